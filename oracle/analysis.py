@@ -1,0 +1,106 @@
+"""Measurement procedures of Sec. 3 applied to density / pressure fields.
+
+TEST INFRASTRUCTURE (see the package docstring).  Fields may come from the
+oracle or from the HIP library; these functions only post-process them.
+"""
+import math
+
+import numpy as np
+from scipy.optimize import curve_fit
+
+
+def bond_number(rho, g, L, D, sigma):
+    """Eq. 15: ratio of the driving to the capillary force, rho g L D / sigma."""
+    return rho * g * L * D / sigma
+
+
+def tanh_profile(x, c1, c2, c3, c4):
+    """Eq. 12: rho(x) = C1 tanh(C2 (x - C3)) + C4."""
+    return c1 * np.tanh(c2 * (x - c3)) + c4
+
+
+def fit_interface(x, rho, guess_pos):
+    """Fit Eq. 12 to a density profile crossing one interface near guess_pos;
+    returns (C1, C2, C3, C4) with C3 the interface position."""
+    x = np.asarray(x, dtype=float)
+    rho = np.asarray(rho, dtype=float)
+    c1 = 0.5 * (rho.max() - rho.min())
+    c4 = 0.5 * (rho.max() + rho.min())
+    left = rho[np.argmin(np.abs(x - (guess_pos - 3)))]
+    sign = -1.0 if left > c4 else 1.0
+    p, _ = curve_fit(tanh_profile, x, rho, p0=(c1, sign * 0.5, guess_pos, c4), maxfev=20000)
+    return p
+
+
+def droplet_radius_from_mass(rho_o, rho_hi, rho_lo):
+    """Radius of a 2-D droplet from its oil mass: the area whose density is
+    rho_hi instead of rho_lo, A = (sum rho_o - rho_lo N) / (rho_hi - rho_lo)."""
+    area = (rho_o.sum() - rho_lo * rho_o.size) / (rho_hi - rho_lo)
+    return math.sqrt(area / math.pi)
+
+
+def laplace_fit(inv_r, dp):
+    """Least-squares line dP = sigma / R + b (Eq. 11); returns (sigma, b, R^2)."""
+    inv_r = np.asarray(inv_r, dtype=float)
+    dp = np.asarray(dp, dtype=float)
+    A = np.stack([inv_r, np.ones_like(inv_r)], axis=1)
+    (s, b), *_ = np.linalg.lstsq(A, dp, rcond=None)
+    pred = A @ np.array([s, b])
+    ss_res = float(((dp - pred) ** 2).sum())
+    ss_tot = float(((dp - dp.mean()) ** 2).sum())
+    return float(s), float(b), 1.0 - ss_res / ss_tot
+
+
+def two_layer_poiseuille(eta, h, b, g, nu_core, nu_wall):
+    """Steady velocity of two immiscible layers of equal density between plates
+    at eta = +-h, interface at |eta| = b, body acceleration g: the wall layer
+    u = g (h^2 - eta^2) / (2 nu_wall), the core
+    u = g (b^2 - eta^2) / (2 nu_core) + g (h^2 - b^2) / (2 nu_wall)."""
+    eta = np.abs(np.asarray(eta, dtype=float))
+    wall = g * (h * h - eta * eta) / (2.0 * nu_wall)
+    core = g * (b * b - eta * eta) / (2.0 * nu_core) + g * (h * h - b * b) / (2.0 * nu_wall)
+    return np.where(eta >= b, wall, core)
+
+
+def variable_viscosity_profile(eta, rho, nu, g, h, n_fine=20001):
+    """Steady unidirectional flow between no-slip plates at eta = +-h for a
+    fluid whose density rho(eta) and kinematic viscosity nu(eta) vary across
+    the channel (given at the nodes eta, linearly interpolated): integrating
+    d/deta (rho nu du/deta) = -rho g with du/deta = 0 at eta = 0 and u = 0 at
+    the walls gives u(eta) = int_|eta|^h S(e) / (rho nu)(e) de with
+    S(e) = int_0^e rho g.  Returns u at the nodes."""
+    eta = np.asarray(eta, dtype=float)
+    order = np.argsort(eta)
+    eta_s = eta[order]
+    e = np.linspace(0.0, h, n_fine)
+    # symmetrise about the centre line
+    r = 0.5 * (np.interp(e, eta_s, np.asarray(rho, float)[order])
+               + np.interp(-e, eta_s, np.asarray(rho, float)[order]))
+    v = 0.5 * (np.interp(e, eta_s, np.asarray(nu, float)[order])
+               + np.interp(-e, eta_s, np.asarray(nu, float)[order]))
+    de = e[1] - e[0]
+    S = np.concatenate([[0.0], np.cumsum(0.5 * (r[1:] + r[:-1]) * g * de)])
+    integrand = S / (r * v)
+    tail = np.concatenate([np.cumsum((0.5 * (integrand[1:] + integrand[:-1]) * de)[::-1])[::-1],
+                           [0.0]])
+    return np.interp(np.abs(eta), e, tail)
+
+
+def circle_fit(x, y):
+    """Algebraic least-squares circle through points; returns (xc, yc, R)."""
+    x = np.asarray(x, dtype=float)
+    y = np.asarray(y, dtype=float)
+    A = np.stack([x, y, np.ones_like(x)], axis=1)
+    rhs = x * x + y * y
+    (a, b, c), *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    xc, yc = a / 2.0, b / 2.0
+    return xc, yc, math.sqrt(c + xc * xc + yc * yc)
+
+
+def contact_angle(R, y0, centre_on_oil_side):
+    """Eq. 14 at the contact point of an arc of radius R spanning a channel of
+    half width y0: the tangent makes acos(y0 / R) with the wall (the arctan
+    form of Eq. 14 is the same angle).  The angle through water is that value
+    when the arc's centre lies on the oil side, else its supplement."""
+    a = math.degrees(math.acos(min(1.0, y0 / R)))
+    return a if centre_on_oil_side else 180.0 - a

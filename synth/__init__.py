@@ -1,0 +1,204 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP path.
+
+This module holds no lattice-Boltzmann arithmetic: only geometry voxelisation
+(which nodes are fluid), initial density fields and the parameter sets of the
+workloads.  Both sides of every parity test take their inputs from here.
+
+Geometry conventions (cell centres at integer coordinates):
+  * x is periodic with period nx.
+  * sinusoidal channel: walls at y = y_c +- h(x), h(x) = h0 + a cos(2 pi x / lam),
+    y_c = (ny - 1) / 2; a node is fluid iff |y - y_c| < h(x) (strict; equality
+    is solid).  ny = 2 (h0 + a) + 2 leaves one solid row at each side.
+  * flat channel: the a = 0 case; with ny = 66 and h0 = 32 the fluid rows are
+    1..64, i.e. the wall planes sit half-way between nodes at y = 0.5, 64.5.
+  * box: every node fluid, periodic in x and y.
+Species 0 is oil (the "A" component), species 1 water ("B").
+"""
+import math
+
+import numpy as np
+
+RHO_HI = 1.0   # majority density of a component inside its own phase
+RHO_LO = 0.03  # minority density of the same component in the other phase
+
+# Interaction strength in the paper's sign convention (repulsion: G < 0).  The
+# mean-field coexistence condition ln(rho_hi / rho_lo) = G_c (rho_hi - rho_lo)
+# for 1.0 / 0.03 gives G_c = 3.615.  The workloads use G = -2.7 (past the
+# spinodal G_c rho_tot = 2): it separates the species to about 1.12 / 0.003-0.026
+# and keeps the viscosity-ratio-20 pairs tau = (0.55, 1.5) and (1.5, 0.55)
+# stable from a sharp 1.0 / 0.03 start.
+G_DEFAULT = -2.7
+
+
+# ---------------------------------------------------------------- geometry ---
+def channel_half_width(x, lam, h0, a):
+    return h0 + a * np.cos(2.0 * np.pi * np.asarray(x, dtype=np.float64) / lam)
+
+
+def channel_mask(nx, ny, lam, h0, a):
+    """uint8 [ny, nx] fluid mask of a sinusoidal (a > 0) or flat (a = 0) channel."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    yc = 0.5 * (ny - 1)
+    h = channel_half_width(x, lam, h0, a)
+    return (np.abs(y - yc) < h).astype(np.uint8)
+
+
+def box_mask(nx, ny):
+    return np.ones((ny, nx), dtype=np.uint8)
+
+
+# ---------------------------------------------------------- initial fields ---
+def droplet_field(nx, ny, cx, cy, r, hi=RHO_HI, lo=RHO_LO):
+    """rho0 [2, ny, nx]: species 0 = hi inside the disc (dist < r), lo outside;
+    species 1 mirrored.  Distances use the periodic image nearest the centre."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    dx = np.abs(x - cx)
+    dx = np.minimum(dx, nx - dx)
+    dy = np.abs(y - cy)
+    dy = np.minimum(dy, ny - dy)
+    inside = (dx * dx + dy * dy) < r * r
+    rho = np.empty((2, ny, nx))
+    rho[0] = np.where(inside, hi, lo)
+    rho[1] = np.where(inside, lo, hi)
+    return rho
+
+
+def layers_field(nx, ny, wall_rows, mask, core_species=0, hi=RHO_HI, lo=RHO_LO):
+    """Two-layer channel: the 'wall_rows' fluid rows next to each wall belong to
+    species 1 - core_species, the rest of the fluid to core_species."""
+    rows = np.nonzero(mask.any(axis=1))[0]
+    first, last = rows.min(), rows.max()
+    y = np.arange(ny)[:, None] * np.ones((1, nx), dtype=np.int64)
+    wall_layer = (y < first + wall_rows) | (y > last - wall_rows)
+    core = ~wall_layer
+    rho = np.empty((2, ny, nx))
+    a, b = core_species, 1 - core_species
+    rho[a] = np.where(core, hi, lo)
+    rho[b] = np.where(core, lo, hi)
+    rho *= mask[None, :, :]
+    return rho
+
+
+def slug_field(nx, ny, x0, length, mask, hi=RHO_HI, lo=RHO_LO):
+    """Oil slug: fluid nodes with x in [x0, x0 + length) (periodic) are oil."""
+    x = np.arange(nx)[None, :] * np.ones((ny, 1), dtype=np.int64)
+    rel = np.mod(x - x0, nx)
+    oil = rel < length
+    rho = np.empty((2, ny, nx))
+    rho[0] = np.where(oil, hi, lo)
+    rho[1] = np.where(oil, lo, hi)
+    rho *= mask[None, :, :]
+    return rho
+
+
+def random_field(nx, ny, mask, seed, mean=(0.5, 0.5), amp=0.05):
+    """Smoothly random densities (for tiny brute-force cross-checks)."""
+    rng = np.random.default_rng(seed)
+    rho = np.empty((2, ny, nx))
+    for s in range(2):
+        rho[s] = mean[s] * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(ny, nx)))
+    return rho * mask[None, :, :]
+
+
+def random_populations(nx, ny, mask, seed, amp=0.02):
+    """Random non-equilibrium populations: w_i * rho0 * (1 + noise) per node.
+    Returns f [2, 9, ny, nx] (float64); solid nodes are 0."""
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    rng = np.random.default_rng(seed)
+    base = 0.2 + 0.8 * rng.uniform(size=(2, 1, ny, nx))
+    f = w[None, :, None, None] * base * (1.0 + amp * rng.uniform(-1, 1, size=(2, 9, ny, nx)))
+    return f * mask[None, None, :, :]
+
+
+# -------------------------------------------------------------- wettability ---
+WALL_SCALE = 0.5
+
+
+def wall_potentials_for_angle(theta_deg, hi=RHO_HI, lo=RHO_LO, scale=WALL_SCALE):
+    """First-guess wall potentials (rho_s^o, rho_s^w) for a contact angle theta
+    measured through water.  The wall is made to look like a scaled mixture of
+    the two bulk phases with oil fraction phi = (1 - cos theta) / 2:
+        rho_s^o = scale ((1 - phi) lo + phi hi),  rho_s^w = scale (phi lo + (1 - phi) hi),
+    so rho_s^w - rho_s^o = scale (hi - lo) cos theta, both potentials are
+    positive, and theta = 90 deg gives equal potentials.  This is a starting
+    map, not a calibration."""
+    phi = 0.5 * (1.0 - math.cos(math.radians(theta_deg)))
+    return (scale * ((1.0 - phi) * lo + phi * hi), scale * (phi * lo + (1.0 - phi) * hi))
+
+
+# ------------------------------------------------------------------ configs ---
+def config_droplet(n=128, r=20.0, tau=(1.0, 1.0), G=G_DEFAULT):
+    """Free droplet on a periodic n x n box."""
+    return dict(name="droplet", nx=n, ny=n, kind="box", lam=0.0, h0=0.0, a=0.0,
+                tau=tau, G=G, rho_s=(0.0, 0.0), g=(0.0, 0.0),
+                init=dict(kind="droplet", cx=n / 2, cy=n / 2, r=r))
+
+
+def config_poiseuille(nx=256, width=64, tau=(0.6, 1.5), g=1e-6, wall_rows=16,
+                      core_species=0, G=G_DEFAULT):
+    """Two-layer Poiseuille: flat channel of `width` fluid rows, species
+    1 - core_species in `wall_rows` rows next to each wall."""
+    ny = width + 2
+    return dict(name="poiseuille", nx=nx, ny=ny, kind="channel", lam=float(nx),
+                h0=width / 2.0, a=0.0, tau=tau, G=G, rho_s=(0.0, 0.0), g=(g, 0.0),
+                init=dict(kind="layers", wall_rows=wall_rows, core_species=core_species))
+
+
+def config_channel(lam=256, theta=90.0, tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug_len=None,
+                   slug_x0=None, h0=None, a=None):
+    """Sinusoidal channel of four wavelengths with an oil slug."""
+    h0 = lam // 8 if h0 is None else h0
+    a = lam // 16 if a is None else a
+    nx = 4 * lam
+    ny = 2 * (h0 + a) + 2
+    slug_len = int(1.5 * lam) if slug_len is None else slug_len
+    slug_x0 = lam // 4 if slug_x0 is None else slug_x0
+    return dict(name="channel", nx=nx, ny=ny, kind="channel", lam=float(lam), h0=float(h0),
+                a=float(a), tau=tau, G=G, rho_s=wall_potentials_for_angle(theta),
+                g=(g, 0.0), theta=theta,
+                init=dict(kind="slug", x0=slug_x0, length=slug_len))
+
+
+def config_batch(n_inst=256, seed=1601, lams=(64, 128, 256, 512), G=G_DEFAULT,
+                 sigma=0.05, rho_bar=1.03):
+    """The batch of uneven channels: lam ~ U{lams}, h0 = lam/8, a = lam/16,
+    theta ~ U(30, 150) deg, viscosity ratio M = nu_o / nu_w ~ logU(0.1, 10)
+    split symmetrically between the two relaxation times, Bond number
+    ~ logU(10^-1.5, 10^1.5) converted to a body acceleration with the given
+    surface-tension scale sigma: g = Bo sigma / (rho_bar * 4 lam * (h0 - a))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_inst):
+        lam = int(rng.choice(lams))
+        theta = float(rng.uniform(30.0, 150.0))
+        m = float(10.0 ** rng.uniform(-1.0, 1.0))
+        bo = float(10.0 ** rng.uniform(-1.5, 1.5))
+        tau = (0.5 + 0.5 * math.sqrt(m), 0.5 + 0.5 / math.sqrt(m))
+        h0, a = lam // 8, lam // 16
+        g = bo * sigma / (rho_bar * 4 * lam * (h0 - a))
+        cfg = config_channel(lam=lam, theta=theta, tau=tau, g=g, G=G)
+        cfg["M"] = m
+        cfg["Bo"] = bo
+        out.append(cfg)
+    return out
+
+
+def mask_of(cfg):
+    if cfg["kind"] == "box":
+        return box_mask(cfg["nx"], cfg["ny"])
+    return channel_mask(cfg["nx"], cfg["ny"], cfg["lam"], cfg["h0"], cfg["a"])
+
+
+def rho0_of(cfg, mask=None):
+    mask = mask_of(cfg) if mask is None else mask
+    ini = cfg["init"]
+    nx, ny = cfg["nx"], cfg["ny"]
+    if ini["kind"] == "droplet":
+        return droplet_field(nx, ny, ini["cx"], ini["cy"], ini["r"])
+    if ini["kind"] == "layers":
+        return layers_field(nx, ny, ini["wall_rows"], mask, ini.get("core_species", 0))
+    if ini["kind"] == "slug":
+        return slug_field(nx, ny, ini["x0"], ini["length"], mask)
+    raise ValueError(ini["kind"])

@@ -1,0 +1,175 @@
+"""Physics pins of the oracle: laws and closed forms the paper validates against
+(Laplace law, two-layer Poiseuille, quiescent flat interface), the Young-Laplace
+critical pressure the paper compares with (Eq. 16, Tables 3-5), and the Bond
+number arithmetic it prints (Eqs. 15, 18).  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import analysis
+from oracle import lbm as orc
+from oracle import young_laplace as yl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+T0 = 1.0 / 3.0
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ------------------------------------------------------------- Bond number --
+def test_bond_arithmetic_printed_values():
+    d = _load("bond_arithmetic.json")
+    rho, L, D, s = d["rho"], d["L"], d["D"], d["sigma"]
+    for g, want in zip(d["worked"]["g"], d["worked"]["bo"]):
+        assert abs(analysis.bond_number(rho, g, L, D, s) - want) <= 0.006
+    assert abs(analysis.bond_number(rho, d["ramp_start"]["g"], L, D, s)
+               - d["ramp_start"]["bo"]) <= 0.005
+    assert abs(rho * d["head"]["g"] * d["head"]["x"] - d["head"]["value"]) <= 5e-6
+    # the printed ramp increment "1.98e-5" is inconsistent with Delta Bo = 0.02;
+    # the consistent increment is 1.98e-6 (matches g = 1.47 -> 1.55 -> 1.57e-4)
+    dg = d["ramp_step"]["dbo"] * s / (rho * L * D)
+    assert abs(dg - 1.98e-6) < 0.01e-6
+
+
+# ---------------------------------------------------- Young-Laplace analytic --
+@pytest.mark.parametrize("case", _load("analytic_bond.json")["cases"],
+                         ids=lambda c: c["cite"])
+def test_young_laplace_reproduces_printed_analytic_bo(case):
+    """The paper's analytic critical Bo (no contact-angle variation) for its
+    sinusoidal tube, to the two decimals it prints."""
+    bo = yl.bond_critical_tube(case["theta"], case["volume"])
+    lo, hi = case["bo"]
+    assert lo - 0.006 <= bo <= hi + 0.006, (case, bo)
+
+
+def test_young_laplace_straight_channel_has_no_barrier():
+    """With a = 0 both menisci carry the same pressure: no static resistance."""
+    ch = yl.Channel(10.0, 0.0, 40.0, axisymmetric=False)
+    dp, _ = yl.critical_pressure(ch, 60.0, 600.0)
+    assert abs(dp) < 1e-12
+
+
+def test_young_laplace_neutral_planar_closed_form():
+    """theta = 90 deg: each planar meniscus carries sigma sin(+-phi) / h, so
+    the critical pressure is bounded by 2 max|sin phi| / h_min."""
+    lam, h0, a = 256.0, 32.0, 16.0
+    dp, bo = yl.bond_critical_channel(lam, h0, a, 90.0, 2 * h0 * 1.5 * lam)
+    k = 2 * math.pi / lam
+    bound = 2 * math.sin(math.atan(a * k)) / (h0 - a)
+    assert 0 < dp <= bound
+    assert abs(bo - dp * (h0 - a)) < 1e-15
+
+
+# ------------------------------------------------------------- LBM physics --
+def test_flat_interface_stays_at_rest():
+    """A flat oil band in water on a periodic lattice: by mirror symmetry the
+    x velocity is identically zero, the y velocity relaxes to (near) zero and
+    the interface position (Eq. 12 fit) does not drift."""
+    nx, ny = 4, 64
+    mask = synth.box_mask(nx, ny)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    oil = (y >= 16) & (y < 48)
+    rho0 = np.stack([np.where(oil, 1.0, 0.03), np.where(oil, 0.03, 1.0)])
+    L = orc.Lattice(orc.Params(nx, ny, tau=(1.0, 1.0), G=synth.G_DEFAULT, periodic_y=True),
+                    mask, rho0)
+    L.step(4000)
+    m1 = L.moments()
+    assert np.abs(m1["u"][0]).max() == 0.0
+    c3a = analysis.fit_interface(np.arange(ny), m1["rho"][0][:, 0], 15.5)[2]
+    L.step(10000)
+    m2 = L.moments()
+    assert np.abs(m2["u"][0]).max() == 0.0
+    assert np.abs(m2["u"][1]).max() < 1e-12 * max(1.0, np.abs(m1["u"][1]).max() / 1e-6)
+    c3b = analysis.fit_interface(np.arange(ny), m2["rho"][0][:, 0], 15.5)[2]
+    assert abs(c3b - c3a) < 1e-4
+    assert abs(c3b - 15.5) < 0.05
+
+
+@pytest.mark.slow
+def test_laplace_law():
+    """Eq. 11: the pressure jump across a static droplet is linear in 1/R
+    through the origin (Sec. 3.1)."""
+    n = 64
+    inv_r, dps = [], []
+    for r0 in (8.0, 11.0, 14.0, 17.0):
+        cfg = synth.config_droplet(n=n, r=r0)
+        mask = synth.mask_of(cfg)
+        L = orc.Lattice(orc.Params(n, n, tau=(1.0, 1.0), G=cfg["G"], periodic_y=True), mask,
+                        synth.rho0_of(cfg, mask))
+        L.step(4000)
+        m = L.moments()
+        c = n // 2
+        rho_hi = m["rho"][0][c, c]
+        rho_lo = m["rho"][0][0, 0]
+        R = analysis.droplet_radius_from_mass(m["rho"][0], rho_hi, rho_lo)
+        inv_r.append(1.0 / R)
+        dps.append(m["p"][c, c] - m["p"][0, 0])
+    sigma, b, r2 = analysis.laplace_fit(inv_r, dps)
+    assert r2 > 0.999
+    assert sigma > 0
+    assert abs(b) < 0.05 * sigma * max(inv_r)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("core_species", [0, 1])
+def test_two_layer_poiseuille(core_species):
+    """Two immiscible layers driven by a body force between no-slip walls
+    (Sec. 3.2), viscosity ratio 1:10 (tau 0.6 / 1.5), both arrangements of the
+    paper.  The steady profile must equal the exact Stokes solution for the
+    measured density and mixed-viscosity profiles (Eqs. 4-5), and follow the
+    sharp-interface two-layer closed form up to the width of the diffuse
+    interface."""
+    nx, width, g = 4, 64, 1e-6
+    cfg = synth.config_poiseuille(nx=nx, width=width, g=g, core_species=core_species)
+    mask = synth.mask_of(cfg)
+    p = orc.Params(nx, cfg["ny"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"], g=cfg["g"])
+    L = orc.Lattice(p, mask, synth.rho0_of(cfg, mask))
+    L.step(60000)
+    m = L.moments()
+    ny = cfg["ny"]
+    eta = np.arange(ny) - 0.5 * (ny - 1)
+    fluid = mask[:, 0] == 1
+    u = m["u"][0][:, 0]
+    ro, rw = m["rho"][0][:, 0], m["rho"][1][:, 0]
+    nu_mix = np.array([T0 * (orc.tau_mix(p, a, b) - 0.5) if a + b > 0 else 1.0
+                       for a, b in zip(ro, rw)])
+    exact = analysis.variable_viscosity_profile(eta[fluid], (ro + rw)[fluid], nu_mix[fluid], g,
+                                                width / 2.0)
+    err_exact = np.abs(u[fluid] - exact).max() / np.abs(exact).max()
+    core = m["rho"][core_species][:, 0]
+    upper = eta > 0
+    c3 = analysis.fit_interface(eta[upper & fluid], core[upper & fluid], 16.0)[2]
+    nu = [T0 * (t - 0.5) for t in cfg["tau"]]
+    sharp = analysis.two_layer_poiseuille(eta, width / 2.0, abs(c3), g,
+                                          nu[core_species], nu[1 - core_species])
+    err_sharp = np.sqrt(np.mean((u[fluid] - sharp[fluid]) ** 2)) / np.abs(sharp[fluid]).max()
+    print("two-layer Poiseuille: vs variable-viscosity solution %.2e, vs sharp closed form "
+          "%.3f (interface %.2f)" % (err_exact, err_sharp, c3))
+    assert err_exact < 1e-2
+    assert err_sharp < 0.12
+
+
+def test_single_component_poiseuille():
+    """One component fills the channel (the other at trace density): the
+    steady profile is the parabola u = g (h^2 - eta^2) / (2 nu) with the
+    half-way bounce-back walls at eta = +-h."""
+    nx, width, g = 4, 32, 1e-6
+    ny = width + 2
+    mask = synth.channel_mask(nx, ny, float(nx), width / 2.0, 0.0)
+    rho0 = np.stack([np.ones((ny, nx)), np.full((ny, nx), 1e-6)]) * mask[None]
+    L = orc.Lattice(orc.Params(nx, ny, tau=(0.8, 0.8), G=0.0, g=(g, 0.0)), mask, rho0)
+    L.step(30000)
+    u = L.moments()["u"][0][:, 0]
+    eta = np.arange(ny) - 0.5 * (ny - 1)
+    nu = T0 * 0.3
+    want = g * ((width / 2.0) ** 2 - eta ** 2) / (2 * nu)
+    fluid = mask[:, 0] == 1
+    err = np.abs(u[fluid] - want[fluid]).max() / want.max()
+    assert err < 2e-3
