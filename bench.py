@@ -1,0 +1,141 @@
+"""Benchmark of the fused two-component D2Q9 step on one MI355X.
+
+Workload (default): the batch of 256 uneven sinusoidal channels (lambda drawn
+from {64, 128, 256, 512}, h0 = lambda/8, a = lambda/16, contact angle, viscosity
+ratio and forcing drawn per instance with numpy default_rng(1601)), all
+advanced together, FP32 populations.  One step = one pass of the whole hot path
+(moments, density halo, interaction and wall force, mixture state, regularized
+collision, streaming with bounce-back) over every instance.
+
+Prints one JSON line: MLUPS (fluid-node updates per second, both species per
+update), the HBM roofline of the step kernel, and the FP64 oracle timed on the
+host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2-comp MLUPS & % HBM roofline; critical-pressure solves/hr batched vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"f32": 144, "f16": 72, "bf16": 72}
+
+
+def workload(name):
+    import synth
+    if name == "batch":
+        cfgs = synth.config_batch(n_inst=256, seed=1601)
+        desc = ("batch of 256 sinusoidal channels, lambda ~ U{64,128,256,512}, h0 = lambda/8, "
+                "a = lambda/16, theta ~ U(30,150) deg, viscosity ratio ~ logU(0.1,10), "
+                "Bo ~ logU(10^-1.5,10^1.5), default_rng(1601)")
+    elif name == "channel":
+        cfgs = [synth.config_channel(lam=256, theta=90.0, g=2e-6)]
+        desc = "sinusoidal channel lambda=256, h0=32, a=16, 1024x98, slug 1.5 lambda"
+    elif name == "poiseuille":
+        cfgs = [synth.config_poiseuille()]
+        desc = "two-layer Poiseuille 256x64 (+2 wall rows), tau 0.6/1.5, g=1e-6"
+    elif name == "droplet":
+        cfgs = [synth.config_droplet(n=128, r=20.0)]
+        desc = "free droplet 128x128 periodic, R=20"
+    else:
+        raise SystemExit("unknown workload %r" % name)
+    return cfgs, desc
+
+
+def fluid_nodes(cfgs):
+    import synth
+    return int(sum(int(synth.mask_of(c).sum()) for c in cfgs))
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle on a bounded sample of the batch: the lambda = 128
+    instances' shape (512 x 50), stepped until about `seconds` have passed."""
+    import numpy as np  # noqa: F401
+    import synth
+    from oracle import lbm as orc
+
+    cfg = synth.config_channel(lam=128, theta=60.0, g=1e-6, tau=(0.8, 1.2))
+    mask = synth.mask_of(cfg)
+    L = orc.Lattice(orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"],
+                               rho_s=cfg["rho_s"], g=cfg["g"]), mask, synth.rho0_of(cfg, mask))
+    nf = int(mask.sum())
+    L.step(2)
+    t0 = time.perf_counter()
+    L.step(10)
+    dt = time.perf_counter() - t0
+    n = max(10, int(seconds / max(dt / 10, 1e-6)))
+    t0 = time.perf_counter()
+    L.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": nf * n / dt / 1e6, "unit": "MLUPS", "cores": orc.threads_used(),
+            "kind": "oracle",
+            "sample": "FP64 oracle, one lambda=128 channel of the batch (512x50, %d fluid nodes), "
+                      "%d steps in %.1f s" % (nf, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1601_00918_amd import Simulation
+
+    cfgs, desc = workload(args.workload)
+    nf = fluid_nodes(cfgs)
+    sim = Simulation(cfgs, storage=args.storage)
+    print("bench: %s, %d instances, %d fluid nodes, workspace %.2f GB" %
+          (args.workload, len(cfgs), nf, sim.workspace_bytes / 1e9), file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    mlups = nf * args.steps / (ms / 1e3) / 1e6
+    mon = sim.monitors()
+    bad = sum(m["bad_nodes"] for m in mon)
+    print("bench: %.4f ms/step (events), wall %.3f s, %.0f MLUPS, bad nodes %d" %
+          (ms_per_step, wall, mlups, bad), file=sys.stderr, flush=True)
+
+    bytes_per_launch = BYTES_PER_NODE[args.storage] * nf
+    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": desc, "instances": len(cfgs), "fluid_nodes": nf,
+                   "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,103 @@
+"""ctypes declarations of the C ABI in include/lbm.h (argument marshalling only).
+
+Loading fails loudly when ``liblbm.so`` has not been built: there is no
+fallback implementation of any entry point.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK = 0
+STATUS_NAMES = {0: "LBM_OK", 1: "LBM_ERR_INVALID", 2: "LBM_ERR_DEVICE", 3: "LBM_ERR_OOM",
+                4: "LBM_ERR_UNSTABLE", 5: "LBM_ERR_BUDGET", 6: "LBM_ERR_UNSUPPORTED"}
+
+GEOM_BOX, GEOM_CHANNEL, GEOM_MASK = 0, 1, 2
+INIT_UNIFORM, INIT_DROPLET, INIT_LAYERS, INIT_SLUG, INIT_FIELD = 0, 1, 2, 3, 4
+STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
+
+# Every symbol include/lbm.h declares.
+EXPORTED = [
+    "lbm_last_error", "lbm_version", "lbm_required_bytes", "lbm_init", "lbm_step",
+    "lbm_time", "lbm_set_fluid", "lbm_moments", "lbm_monitors", "lbm_get_populations",
+    "lbm_fluid_mask", "lbm_destroy",
+]
+
+
+class LbmGeom(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lam", ctypes.c_double), ("h0", ctypes.c_double),
+                ("a", ctypes.c_double), ("mask", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class LbmFluid(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double * 2), ("G", ctypes.c_double),
+                ("rho_s", ctypes.c_double * 2), ("g", ctypes.c_double * 2)]
+
+
+class LbmInitFields(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("wall_rows", ctypes.c_int32),
+                ("core_species", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("r", ctypes.c_double),
+                ("x0", ctypes.c_double), ("length", ctypes.c_double),
+                ("rho0", ctypes.POINTER(ctypes.c_double))]
+
+
+class LbmMonitor(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double * 2), ("momentum", ctypes.c_double * 2),
+                ("oil_flux", ctypes.c_double), ("oil_cos", ctypes.c_double),
+                ("oil_sin", ctypes.c_double), ("bad_nodes", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load():
+    """Load liblbm.so (raises if it is missing)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblbm.so is not built (expected at %s); run "
+                          "paper_1601_00918_amd/build.py or __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_version.restype = ctypes.c_char_p
+    lib.lbm_version.argtypes = []
+    lib.lbm_required_bytes.argtypes = [ctypes.POINTER(LbmGeom), i32, i32, ctypes.POINTER(sz)]
+    lib.lbm_init.argtypes = [ctypes.POINTER(LbmGeom), ctypes.POINTER(LbmFluid),
+                             ctypes.POINTER(LbmInitFields), i32, i32, vp, sz, vp,
+                             ctypes.POINTER(vp)]
+    lib.lbm_step.argtypes = [vp, i64]
+    lib.lbm_time.argtypes = [vp]
+    lib.lbm_time.restype = i64
+    lib.lbm_set_fluid.argtypes = [vp, i32, ctypes.POINTER(LbmFluid)]
+    lib.lbm_moments.argtypes = [vp, i32, dp, dp, dp, ctypes.POINTER(LbmMonitor)]
+    lib.lbm_monitors.argtypes = [vp, ctypes.POINTER(LbmMonitor)]
+    lib.lbm_get_populations.argtypes = [vp, i32, dp]
+    lib.lbm_fluid_mask.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint8)]
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, where):
+        msg = load().lbm_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def check(status, where):
+    if status != LBM_OK:
+        raise LbmError(status, where)

@@ -1,0 +1,227 @@
+"""Thin Python binding over the C ABI (include/lbm.h).
+
+Argument marshalling only: numpy arrays are passed as host pointers, torch
+provides the device workspace (``torch.empty(..., dtype=torch.uint8)``) and the
+HIP stream (``torch.cuda.current_stream().cuda_stream``).
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GEOM_BOX, GEOM_CHANNEL, GEOM_MASK, INIT_DROPLET, INIT_FIELD, INIT_LAYERS,
+                   INIT_SLUG, INIT_UNIFORM, STORE_BF16, STORE_F16, STORE_F32, LbmFluid, LbmGeom,
+                   LbmInitFields, LbmMonitor, check)
+
+_GEOM_KINDS = {"box": GEOM_BOX, "channel": GEOM_CHANNEL, "mask": GEOM_MASK}
+_INIT_KINDS = {"uniform": INIT_UNIFORM, "droplet": INIT_DROPLET, "layers": INIT_LAYERS,
+               "slug": INIT_SLUG, "field": INIT_FIELD}
+_STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
+
+
+def lbm_version():
+    return _lib.load().lbm_version().decode()
+
+
+# ------------------------------------------------------------- structs -------
+def geom_struct(kind, nx, ny, lam=0.0, h0=0.0, a=0.0, mask=None, _keep=None):
+    g = LbmGeom()
+    g.kind = _GEOM_KINDS[kind] if isinstance(kind, str) else int(kind)
+    g.nx, g.ny = int(nx), int(ny)
+    g.lam, g.h0, g.a = float(lam), float(h0), float(a)
+    if mask is not None:
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape == (ny, nx)
+        if _keep is not None:
+            _keep.append(m)
+        g.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    return g
+
+
+def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0)):
+    f = LbmFluid()
+    f.tau[0], f.tau[1] = float(tau[0]), float(tau[1])
+    f.G = float(G)
+    f.rho_s[0], f.rho_s[1] = float(rho_s[0]), float(rho_s[1])
+    f.g[0], f.g[1] = float(g[0]), float(g[1])
+    return f
+
+
+def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=0,
+                core_species=0, x0=0.0, length=0.0, rho0=None, _keep=None):
+    s = LbmInitFields()
+    s.kind = _INIT_KINDS[kind] if isinstance(kind, str) else int(kind)
+    s.rho_hi, s.rho_lo = float(rho_hi), float(rho_lo)
+    s.cx, s.cy, s.r = float(cx), float(cy), float(r)
+    s.wall_rows, s.core_species = int(wall_rows), int(core_species)
+    s.x0, s.length = float(x0), float(length)
+    if rho0 is not None:
+        a = np.ascontiguousarray(rho0, dtype=np.float64)
+        if _keep is not None:
+            _keep.append(a)
+        s.rho0 = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return s
+
+
+def structs_from_config(cfg, rho0=None, keep=None):
+    """(geom, fluid, init) structs from a workload dict; rho0 forces an
+    explicit initial field."""
+    geom = geom_struct(cfg["kind"], cfg["nx"], cfg["ny"], cfg.get("lam", 0.0),
+                       cfg.get("h0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep)
+    fluid = fluid_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)), cfg.get("g", (0, 0)))
+    if rho0 is not None:
+        init = init_struct("field", rho0=rho0, _keep=keep)
+    else:
+        ini = dict(cfg["init"])
+        kind = ini.pop("kind")
+        init = init_struct(kind, **ini)
+    return geom, fluid, init
+
+
+# ------------------------------------------------------------- ABI calls -----
+def _arr(structs, typ):
+    a = (typ * len(structs))()
+    for k, s in enumerate(structs):
+        a[k] = s
+    return a
+
+
+def lbm_required_bytes(geoms, storage="f32"):
+    n = ctypes.c_size_t()
+    ga = _arr(geoms, LbmGeom)
+    check(_lib.load().lbm_required_bytes(ga, len(geoms), _STORAGE[storage], ctypes.byref(n)),
+          "lbm_required_bytes")
+    return n.value
+
+
+def lbm_init(geoms, fluids, inits, storage, workspace_ptr, workspace_bytes, stream_ptr):
+    ctx = ctypes.c_void_p()
+    check(_lib.load().lbm_init(_arr(geoms, LbmGeom), _arr(fluids, LbmFluid),
+                               _arr(inits, LbmInitFields), len(geoms), _STORAGE[storage],
+                               ctypes.c_void_p(workspace_ptr), workspace_bytes,
+                               ctypes.c_void_p(stream_ptr), ctypes.byref(ctx)), "lbm_init")
+    return ctx
+
+
+def lbm_step(ctx, nsteps):
+    check(_lib.load().lbm_step(ctx, int(nsteps)), "lbm_step")
+
+
+def lbm_time(ctx):
+    return _lib.load().lbm_time(ctx)
+
+
+def lbm_set_fluid(ctx, inst, fluid):
+    check(_lib.load().lbm_set_fluid(ctx, int(inst), ctypes.byref(fluid)), "lbm_set_fluid")
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _monitor_dict(m):
+    return {"mass": (m.mass[0], m.mass[1]), "momentum": (m.momentum[0], m.momentum[1]),
+            "oil_flux": m.oil_flux, "oil_cos": m.oil_cos, "oil_sin": m.oil_sin,
+            "bad_nodes": m.bad_nodes}
+
+
+def lbm_moments(ctx, inst, nx, ny):
+    rho = np.zeros((2, ny, nx))
+    u = np.zeros((2, ny, nx))
+    p = np.zeros((ny, nx))
+    mon = LbmMonitor()
+    check(_lib.load().lbm_moments(ctx, int(inst), _dp(rho), _dp(u), _dp(p), ctypes.byref(mon)),
+          "lbm_moments")
+    return {"rho": rho, "u": u, "p": p, "mon": _monitor_dict(mon)}
+
+
+def lbm_monitors(ctx, n_inst):
+    arr = (LbmMonitor * n_inst)()
+    check(_lib.load().lbm_monitors(ctx, arr), "lbm_monitors")
+    return [_monitor_dict(m) for m in arr]
+
+
+def lbm_get_populations(ctx, inst, nx, ny):
+    f = np.zeros((2, 9, ny, nx))
+    check(_lib.load().lbm_get_populations(ctx, int(inst), _dp(f)), "lbm_get_populations")
+    return f
+
+
+def lbm_fluid_mask(ctx, inst, nx, ny):
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    check(_lib.load().lbm_fluid_mask(ctx, int(inst),
+                                     m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+          "lbm_fluid_mask")
+    return m
+
+
+def lbm_destroy(ctx):
+    _lib.load().lbm_destroy(ctx)
+
+
+# ------------------------------------------------------------- convenience ---
+class Simulation:
+    """A context plus the torch device workspace that backs it.
+
+    configs: list of workload dicts (keys nx, ny, kind, lam, h0, a, tau, G,
+    rho_s, g, init); fields: optional list (same length) of explicit initial
+    density arrays [2, ny, nx] (None entries use the config's preset)."""
+
+    def __init__(self, configs, fields=None, storage="f32", device="cuda"):
+        import torch  # device memory and streams only
+
+        _lib.load()
+        self.configs = list(configs)
+        keep = []
+        geoms, fluids, inits = [], [], []
+        for k, cfg in enumerate(self.configs):
+            rho0 = None if fields is None else fields[k]
+            g, f, i = structs_from_config(cfg, rho0, keep)
+            geoms.append(g)
+            fluids.append(f)
+            inits.append(i)
+        self.fluids = fluids
+        nbytes = lbm_required_bytes(geoms, storage)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        self.ctx = lbm_init(geoms, fluids, inits, storage, self.workspace.data_ptr(), nbytes,
+                            self.stream.cuda_stream)
+        self.workspace_bytes = nbytes
+        del keep
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            lbm_destroy(ctx)
+            self.ctx = None
+
+    @property
+    def n_inst(self):
+        return len(self.configs)
+
+    @property
+    def t(self):
+        return lbm_time(self.ctx)
+
+    def step(self, nsteps=1):
+        lbm_step(self.ctx, nsteps)
+
+    def set_body_force(self, inst, gx, gy=0.0):
+        f = self.fluids[inst]
+        f.g[0], f.g[1] = float(gx), float(gy)
+        lbm_set_fluid(self.ctx, inst, f)
+
+    def moments(self, inst=0):
+        c = self.configs[inst]
+        return lbm_moments(self.ctx, inst, c["nx"], c["ny"])
+
+    def monitors(self):
+        return lbm_monitors(self.ctx, self.n_inst)
+
+    def populations(self, inst=0):
+        c = self.configs[inst]
+        return lbm_get_populations(self.ctx, inst, c["nx"], c["ny"])
+
+    def fluid_mask(self, inst=0):
+        c = self.configs[inst]
+        return lbm_fluid_mask(self.ctx, inst, c["nx"], c["ny"])

@@ -1,0 +1,584 @@
+// Host runtime behind the C ABI of include/lbm.h: parameter validation,
+// voxelisation into column runs, work-item tiling, workspace carving, launch
+// sequencing and device-to-host export.
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LBM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMinBx = 64;
+constexpr int kMinStrip = 8;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Host description of one instance.
+struct InstHost {
+    int kind;
+    int nx, ny;
+    int pitch;
+    int64_t plane;
+    int64_t f_off;
+    std::vector<Col> cols;  // per column fluid run
+};
+
+// Fluid runs per column for a geometry; returns false with a message on error.
+bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
+{
+    cols.assign(g.nx, Col{0, -1});
+    if (g.kind == LBM_GEOM_BOX) {
+        for (auto& c : cols)
+            c = Col{0, g.ny - 1};
+        return true;
+    }
+    if (g.kind == LBM_GEOM_CHANNEL) {
+        const double yc = 0.5 * (g.ny - 1);
+        for (int x = 0; x < g.nx; ++x) {
+            const double h = g.h0 + g.a * std::cos(2.0 * M_PI * (double)x / g.lambda);
+            int lo = g.ny, hi = -1;
+            for (int y = 0; y < g.ny; ++y)
+                if (std::fabs((double)y - yc) < h) {
+                    lo = std::min(lo, y);
+                    hi = std::max(hi, y);
+                }
+            cols[x] = lo <= hi ? Col{lo, hi} : Col{0, -1};
+        }
+        return true;
+    }
+    if (g.kind == LBM_GEOM_MASK) {
+        if (!g.mask) {
+            err = "LBM_GEOM_MASK needs a mask";
+            return false;
+        }
+        for (int x = 0; x < g.nx; ++x) {
+            int lo = -1, hi = -1;
+            for (int y = 0; y < g.ny; ++y)
+                if (g.mask[(size_t)y * g.nx + x]) {
+                    if (lo < 0)
+                        lo = y;
+                    else if (hi != y - 1) {
+                        err = "mask column " + std::to_string(x) +
+                              " has more than one run of fluid rows";
+                        return false;
+                    }
+                    hi = y;
+                }
+            cols[x] = lo >= 0 ? Col{lo, hi} : Col{0, -1};
+        }
+        return true;
+    }
+    err = "unknown geometry kind";
+    return false;
+}
+
+lbm_status check_geom(const lbm_geom& g)
+{
+    if (g.nx < 1 || g.ny < 1 || g.nx > 32768 || g.ny > 32768)
+        return fail(LBM_ERR_INVALID, "geometry size %d x %d out of range", g.nx, g.ny);
+    if (g.kind == LBM_GEOM_BOX) {
+        if (g.ny < 3 || g.nx < 3)
+            return fail(LBM_ERR_INVALID, "box geometry needs nx, ny >= 3");
+        return LBM_OK;
+    }
+    if (g.kind == LBM_GEOM_CHANNEL) {
+        if (!(g.lambda > 0.0) || !(g.h0 > 0.0) || !(g.a >= 0.0) || !std::isfinite(g.h0 + g.a))
+            return fail(LBM_ERR_INVALID, "channel needs lambda > 0, h0 > 0, a >= 0");
+        if (g.nx < 3)
+            return fail(LBM_ERR_INVALID, "channel needs nx >= 3");
+        return LBM_OK;
+    }
+    if (g.kind == LBM_GEOM_MASK) {
+        if (!g.mask)
+            return fail(LBM_ERR_INVALID, "mask geometry without a mask");
+        if (g.nx < 3)
+            return fail(LBM_ERR_INVALID, "mask geometry needs nx >= 3");
+        return LBM_OK;
+    }
+    return fail(LBM_ERR_INVALID, "unknown geometry kind %d", g.kind);
+}
+
+lbm_status check_fluid(const lbm_fluid& f)
+{
+    for (int s = 0; s < 2; ++s) {
+        if (!(f.tau[s] > 0.5) || !std::isfinite(f.tau[s]))
+            return fail(LBM_ERR_INVALID, "tau[%d] = %g must be finite and > 1/2", s, f.tau[s]);
+        if (!std::isfinite(f.rho_s[s]) || f.rho_s[s] < 0.0)
+            return fail(LBM_ERR_INVALID, "rho_s[%d] must be finite and >= 0", s);
+        if (!std::isfinite(f.g[s]) || std::fabs(f.g[s]) > 0.1)
+            return fail(LBM_ERR_INVALID, "|g[%d]| must be <= 0.1", s);
+    }
+    if (!std::isfinite(f.G))
+        return fail(LBM_ERR_INVALID, "G must be finite");
+    return LBM_OK;
+}
+
+int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
+
+int64_t plane_of(int nx, int ny) { return (int64_t)align_up((size_t)pitch_of(nx) * ny, 64); }
+
+size_t elem_size(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
+
+// Upper bound on the number of work items for any supported tiling.
+int64_t max_items(const lbm_geom& g)
+{
+    return (int64_t)((g.nx + kMinBx - 1) / kMinBx) * ((g.ny + kMinStrip - 1) / kMinStrip);
+}
+
+struct Layout {
+    size_t buf_bytes;  // one population buffer
+    size_t off_buf[2], off_inst, off_items, off_cols, off_partial, off_mon, off_first,
+        off_count, off_stage, total;
+    int64_t n_items_max;
+    int64_t max_nodes;
+};
+
+Layout layout_of(const lbm_geom* geoms, int n_inst, int storage)
+{
+    Layout L{};
+    int64_t elems = 0, ncols = 0;
+    L.n_items_max = 0;
+    L.max_nodes = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const lbm_geom& g = geoms[k];
+        elems += 18 * plane_of(g.nx, g.ny);
+        ncols += g.nx;
+        L.n_items_max += max_items(g);
+        L.max_nodes = std::max<int64_t>(L.max_nodes, (int64_t)g.nx * g.ny);
+    }
+    L.buf_bytes = align_up((size_t)elems * elem_size(storage), kAlign);
+    size_t o = 0;
+    L.off_buf[0] = o;
+    o += L.buf_bytes;
+    L.off_buf[1] = o;
+    o += L.buf_bytes;
+    L.off_inst = o;
+    o = align_up(o + sizeof(InstDev) * n_inst, kAlign);
+    L.off_items = o;
+    o = align_up(o + sizeof(Item) * L.n_items_max, kAlign);
+    L.off_cols = o;
+    o = align_up(o + sizeof(Col) * ncols, kAlign);
+    L.off_partial = o;
+    o = align_up(o + sizeof(double) * kMonWidth * L.n_items_max, kAlign);
+    L.off_mon = o;
+    o = align_up(o + sizeof(double) * kMonWidth * n_inst, kAlign);
+    L.off_first = o;
+    o = align_up(o + sizeof(int32_t) * n_inst, kAlign);
+    L.off_count = o;
+    o = align_up(o + sizeof(int32_t) * n_inst, kAlign);
+    L.off_stage = o;
+    o = align_up(o + sizeof(double) * kExportFields * L.max_nodes, kAlign);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    int n_inst = 0;
+    int storage = LBM_STORE_F32;
+    std::vector<InstHost> ih;
+    std::vector<InstDev> idv;
+    std::vector<Item> items;
+    std::vector<int32_t> item_first, item_count;
+    Layout L{};
+    char* ws = nullptr;
+    float* buf[2] = {nullptr, nullptr};
+    InstDev* inst_d = nullptr;
+    Item* items_d = nullptr;
+    Col* cols_d = nullptr;
+    double* partial_d = nullptr;
+    double* mon_d = nullptr;
+    int32_t* first_d = nullptr;
+    int32_t* count_d = nullptr;
+    double* stage_d = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    int64_t t = 0;
+    int bx = 256;
+    int strip = 32;
+};
+
+namespace {
+
+void fill_inst_params(InstDev& d, const lbm_fluid& f)
+{
+    d.tau_h[0] = (float)(f.tau[0] - 0.5);
+    d.tau_h[1] = (float)(f.tau[1] - 0.5);
+    d.G36 = (float)(f.G / 36.0);
+    d.rho_s[0] = (float)f.rho_s[0];
+    d.rho_s[1] = (float)f.rho_s[1];
+    d.g[0] = (float)f.g[0];
+    d.g[1] = (float)f.g[1];
+    d.Gd = f.G;
+}
+
+// Cut every instance into work items: blocks of bx columns, each split into
+// strips of `strip` rows covering the block's fluid rows.
+void build_items(lbm_ctx* c)
+{
+    c->items.clear();
+    c->item_first.assign(c->n_inst, 0);
+    c->item_count.assign(c->n_inst, 0);
+    for (int k = 0; k < c->n_inst; ++k) {
+        const InstHost& h = c->ih[k];
+        c->item_first[k] = (int32_t)c->items.size();
+        for (int x0 = 0; x0 < h.nx; x0 += c->bx) {
+            const int x1 = std::min(h.nx, x0 + c->bx);
+            int ylo = h.ny, yhi = -1;
+            for (int x = x0; x < x1; ++x)
+                if (h.cols[x].lo <= h.cols[x].hi) {
+                    ylo = std::min(ylo, h.cols[x].lo);
+                    yhi = std::max(yhi, h.cols[x].hi);
+                }
+            if (yhi < ylo)
+                continue;
+            for (int y0 = ylo; y0 <= yhi; y0 += c->strip)
+                c->items.push_back(Item{k, x0, y0, std::min(yhi + 1, y0 + c->strip)});
+        }
+        c->item_count[k] = (int32_t)c->items.size() - c->item_first[k];
+    }
+}
+
+lbm_status upload_tables(lbm_ctx* c)
+{
+    HIP_TRY(hipMemcpyAsync(c->items_d, c->items.data(), sizeof(Item) * c->items.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->first_d, c->item_first.data(), sizeof(int32_t) * c->n_inst,
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->count_d, c->item_count.data(), sizeof(int32_t) * c->n_inst,
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status run_mode(lbm_ctx* c, int mode, int item_base, int n_items)
+{
+    hipError_t e = launch_step(c->bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1], c->inst_d,
+                               c->items_d, item_base, n_items, c->cols_d, c->partial_d,
+                               c->stage_d, c->stream);
+    if (e != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "step launch failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+const char* lbm_version(void) { return "mi355x-mclbm 0.1 (gfx950, D2Q9)"; }
+
+lbm_status lbm_required_bytes(const lbm_geom* geoms, int32_t n_inst, int32_t storage,
+                              size_t* bytes)
+{
+    if (!geoms || n_inst < 1 || !bytes)
+        return fail(LBM_ERR_INVALID, "lbm_required_bytes: null argument or n_inst < 1");
+    if (storage != LBM_STORE_F32)
+        return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
+    for (int k = 0; k < n_inst; ++k) {
+        lbm_status st = check_geom(geoms[k]);
+        if (st != LBM_OK)
+            return st;
+    }
+    *bytes = layout_of(geoms, n_inst, storage).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
+                    const lbm_init_fields* inits, int32_t n_inst, int32_t storage,
+                    void* device_workspace, size_t workspace_bytes, void* hip_stream,
+                    lbm_ctx** out)
+{
+    if (!out)
+        return fail(LBM_ERR_INVALID, "lbm_init: out is null");
+    *out = nullptr;
+    if (!geoms || !fluids || !inits || n_inst < 1 || !device_workspace)
+        return fail(LBM_ERR_INVALID, "lbm_init: null argument or n_inst < 1");
+    if (storage != LBM_STORE_F32)
+        return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
+    if ((uintptr_t)device_workspace % kAlign)
+        return fail(LBM_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    for (int k = 0; k < n_inst; ++k) {
+        lbm_status st = check_geom(geoms[k]);
+        if (st != LBM_OK)
+            return st;
+        st = check_fluid(fluids[k]);
+        if (st != LBM_OK)
+            return st;
+        const lbm_init_fields& in = inits[k];
+        if (in.kind < LBM_INIT_UNIFORM || in.kind > LBM_INIT_FIELD)
+            return fail(LBM_ERR_INVALID, "instance %d: unknown init kind %d", k, in.kind);
+        if (in.kind == LBM_INIT_FIELD)
+            return fail(LBM_ERR_UNSUPPORTED,
+                        "instance %d: explicit initial fields (LBM_INIT_FIELD) are switched "
+                        "off in this build; use a preset", k);
+        if (in.kind != LBM_INIT_FIELD &&
+            (!(in.rho_hi > 0.0) || !(in.rho_lo > 0.0) || !std::isfinite(in.rho_hi + in.rho_lo)))
+            return fail(LBM_ERR_INVALID, "instance %d: rho_hi, rho_lo must be > 0", k);
+        if (in.kind == LBM_INIT_LAYERS && (in.core_species < 0 || in.core_species > 1))
+            return fail(LBM_ERR_INVALID, "instance %d: core_species must be 0 or 1", k);
+    }
+    const Layout L = layout_of(geoms, n_inst, storage);
+    if (workspace_bytes < L.total)
+        return fail(LBM_ERR_OOM, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c)
+        return fail(LBM_ERR_INVALID, "out of host memory");
+    c->n_inst = n_inst;
+    c->storage = storage;
+    c->L = L;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)device_workspace;
+    c->buf[0] = (float*)(c->ws + L.off_buf[0]);
+    c->buf[1] = (float*)(c->ws + L.off_buf[1]);
+    c->inst_d = (InstDev*)(c->ws + L.off_inst);
+    c->items_d = (Item*)(c->ws + L.off_items);
+    c->cols_d = (Col*)(c->ws + L.off_cols);
+    c->partial_d = (double*)(c->ws + L.off_partial);
+    c->mon_d = (double*)(c->ws + L.off_mon);
+    c->first_d = (int32_t*)(c->ws + L.off_first);
+    c->count_d = (int32_t*)(c->ws + L.off_count);
+    c->stage_d = (double*)(c->ws + L.off_stage);
+
+    // Instances, column tables.
+    c->ih.resize(n_inst);
+    c->idv.resize(n_inst);
+    std::vector<Col> all_cols;
+    int64_t f_off = 0;
+    int max_nx = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const lbm_geom& g = geoms[k];
+        InstHost& h = c->ih[k];
+        std::string err;
+        if (!voxelise(g, h.cols, err)) {
+            delete c;
+            return fail(LBM_ERR_UNSUPPORTED, "instance %d: %s", k, err.c_str());
+        }
+        h.kind = g.kind;
+        h.nx = g.nx;
+        h.ny = g.ny;
+        h.pitch = pitch_of(g.nx);
+        h.plane = plane_of(g.nx, g.ny);
+        h.f_off = f_off;
+        f_off += 18 * h.plane;
+        max_nx = std::max(max_nx, g.nx);
+        InstDev& d = c->idv[k];
+        std::memset(&d, 0, sizeof d);
+        d.f_off = h.f_off;
+        d.plane = h.plane;
+        d.nx = g.nx;
+        d.ny = g.ny;
+        d.pitch = h.pitch;
+        d.periodic_y = g.kind == LBM_GEOM_BOX ? 1 : 0;
+        d.col_off = (int32_t)all_cols.size();
+        fill_inst_params(d, fluids[k]);
+        all_cols.insert(all_cols.end(), h.cols.begin(), h.cols.end());
+    }
+    // Default tiling: widest block not wider than the widest instance.
+    c->bx = max_nx >= 256 ? 256 : (max_nx >= 128 ? 128 : 64);
+    c->strip = 32;
+    build_items(c);
+
+    lbm_status st = LBM_OK;
+    auto bail = [&](lbm_status s) {
+        delete c;
+        return s;
+    };
+    hipError_t e;
+    if ((e = hipMemcpyAsync(c->inst_d, c->idv.data(), sizeof(InstDev) * n_inst,
+                            hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c->cols_d, all_cols.data(), sizeof(Col) * all_cols.size(),
+                            hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->ws + L.off_buf[0], 0, 2 * L.buf_bytes, c->stream)) !=
+            hipSuccess)
+        return bail(fail(LBM_ERR_DEVICE, "lbm_init upload failed: %s", hipGetErrorString(e)));
+    if ((st = upload_tables(c)) != LBM_OK)
+        return bail(st);
+
+    // Initial state, one instance at a time.
+    for (int k = 0; k < n_inst; ++k) {
+        const lbm_init_fields& in = inits[k];
+        const InstHost& h = c->ih[k];
+        InitDev ini{};
+        ini.kind = in.kind;
+        ini.core_species = in.core_species;
+        ini.wall_rows = in.wall_rows;
+        ini.rho_hi = in.rho_hi;
+        ini.rho_lo = in.rho_lo;
+        ini.cx = in.cx;
+        ini.cy = in.cy;
+        ini.r = in.r;
+        ini.x0 = in.x0;
+        ini.length = in.length;
+        int first = h.ny, last = -1;
+        for (const Col& cc : h.cols)
+            if (cc.lo <= cc.hi) {
+                first = std::min(first, cc.lo);
+                last = std::max(last, cc.hi);
+            }
+        ini.first_row = first;
+        ini.last_row = last;
+        if ((e = launch_init(c->buf[0], c->inst_d, k, c->cols_d, h.nx, h.ny, ini, c->stream)) !=
+            hipSuccess)
+            return bail(fail(LBM_ERR_DEVICE, "init launch failed: %s", hipGetErrorString(e)));
+    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return bail(fail(LBM_ERR_DEVICE, "init failed: %s", hipGetErrorString(e)));
+    c->cur = 0;
+    c->t = 0;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0)
+        return fail(LBM_ERR_INVALID, "lbm_step: null context or negative step count");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        lbm_status st = run_mode(c, kStep, 0, (int)c->items.size());
+        if (st != LBM_OK)
+            return st;
+        c->cur ^= 1;
+        ++c->t;
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_set_fluid(lbm_ctx* c, int32_t inst, const lbm_fluid* fluid)
+{
+    if (!c || !fluid || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_set_fluid: bad argument");
+    lbm_status st = check_fluid(*fluid);
+    if (st != LBM_OK)
+        return st;
+    fill_inst_params(c->idv[inst], *fluid);
+    HIP_TRY(hipMemcpyAsync(c->inst_d + inst, &c->idv[inst], sizeof(InstDev),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_monitors(lbm_ctx* c, lbm_monitor* mon)
+{
+    if (!c || !mon)
+        return fail(LBM_ERR_INVALID, "lbm_monitors: null argument");
+    lbm_status st = run_mode(c, kMonOnly, 0, (int)c->items.size());
+    if (st != LBM_OK)
+        return st;
+    hipError_t e = launch_mon_reduce(c->partial_d, c->first_d, c->count_d, c->n_inst, c->mon_d,
+                                     c->stream);
+    if (e != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "monitor reduce failed: %s", hipGetErrorString(e));
+    static_assert(sizeof(lbm_monitor) == kMonWidth * sizeof(double), "monitor layout");
+    HIP_TRY(hipMemcpyAsync(mon, c->mon_d, sizeof(lbm_monitor) * c->n_inst, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+static lbm_status export_instance(lbm_ctx* c, int inst)
+{
+    const InstHost& h = c->ih[inst];
+    const size_t n = (size_t)h.nx * h.ny;
+    HIP_TRY(hipMemsetAsync(c->stage_d, 0, sizeof(double) * kExportFields * n, c->stream));
+    return run_mode(c, kExport, c->item_first[inst], c->item_count[inst]);
+}
+
+lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* rho, double* u, double* p,
+                       lbm_monitor* mon)
+{
+    if (!c || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_moments: bad argument");
+    const InstHost& h = c->ih[inst];
+    const size_t n = (size_t)h.nx * h.ny;
+    if (rho || u || p) {
+        lbm_status st = export_instance(c, inst);
+        if (st != LBM_OK)
+            return st;
+        if (rho)
+            HIP_TRY(hipMemcpyAsync(rho, c->stage_d + 18 * n, sizeof(double) * 2 * n,
+                                   hipMemcpyDeviceToHost, c->stream));
+        if (u)
+            HIP_TRY(hipMemcpyAsync(u, c->stage_d + 20 * n, sizeof(double) * 2 * n,
+                                   hipMemcpyDeviceToHost, c->stream));
+        if (p)
+            HIP_TRY(hipMemcpyAsync(p, c->stage_d + 22 * n, sizeof(double) * n,
+                                   hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    if (mon) {
+        std::vector<lbm_monitor> all(c->n_inst);
+        lbm_status st = lbm_monitors(c, all.data());
+        if (st != LBM_OK)
+            return st;
+        *mon = all[inst];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, int32_t inst, double* f)
+{
+    if (!c || !f || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_get_populations: bad argument");
+    const InstHost& h = c->ih[inst];
+    const size_t n = (size_t)h.nx * h.ny;
+    lbm_status st = export_instance(c, inst);
+    if (st != LBM_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(f, c->stage_d, sizeof(double) * 18 * n, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_fluid_mask(lbm_ctx* c, int32_t inst, uint8_t* mask)
+{
+    if (!c || !mask || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_fluid_mask: bad argument");
+    const InstHost& h = c->ih[inst];
+    for (int y = 0; y < h.ny; ++y)
+        for (int x = 0; x < h.nx; ++x)
+            mask[(size_t)y * h.nx + x] = (y >= h.cols[x].lo && y <= h.cols[x].hi) ? 1 : 0;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every entry point include/lbm.h declares,
+and its host-side validation works (no GPU needed: nothing here launches a
+kernel or touches device memory)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1601_00918_amd import _lib, binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_list():
+    assert _declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert "gfx950" in binding.lbm_version()
+
+
+def _geom(**kw):
+    d = dict(kind="channel", nx=256, ny=26, lam=64.0, h0=8.0, a=4.0)
+    d.update(kw)
+    return binding.geom_struct(**d)
+
+
+def test_required_bytes_scales_with_storage_of_populations():
+    one = binding.lbm_required_bytes([_geom()])
+    two = binding.lbm_required_bytes([_geom(), _geom()])
+    pops = 2 * 18 * 4 * 256 * 26   # two population buffers, FP32
+    assert one >= pops
+    assert pops <= two - one <= pops + 64 * 1024
+
+
+def test_required_bytes_rejects_bad_geometry():
+    with pytest.raises(_lib.LbmError) as e:
+        binding.lbm_required_bytes([_geom(nx=0)])
+    assert e.value.status == 1 and "out of range" in str(e.value)
+    with pytest.raises(_lib.LbmError):
+        binding.lbm_required_bytes([_geom(h0=-1.0)])
+    with pytest.raises(_lib.LbmError) as e:
+        binding.lbm_required_bytes([_geom()], storage="bf16")
+    assert e.value.status == 6
+
+
+def _try_init(geoms, fluids, inits, ws_bytes=1 << 30):
+    # A fake, aligned, never-dereferenced workspace pointer: every case below
+    # must be rejected on the host before any device work is enqueued.
+    return binding.lbm_init(geoms, fluids, inits, "f32", 1 << 20, ws_bytes, 0)
+
+
+def test_init_rejects_bad_fluid_and_init_on_host():
+    g = [_geom()]
+    ok_init = [binding.init_struct("uniform")]
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, [binding.fluid_struct((0.5, 1.0), -2.7)], ok_init)
+    assert e.value.status == 1 and "tau" in str(e.value)
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7, g=(0.5, 0))], ok_init)
+    assert "g[0]" in str(e.value)
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct("field")])
+    assert e.value.status == 6 and "switched off" in str(e.value)
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], ok_init, ws_bytes=1024)
+    assert e.value.status == 3
+
+
+def test_mask_with_two_fluid_runs_in_a_column_is_unsupported():
+    mask = np.ones((10, 8), dtype=np.uint8)
+    mask[4, 3] = 0
+    keep = []
+    g = binding.geom_struct("mask", 8, 10, mask=mask, _keep=keep)
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init([g], [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct("uniform")])
+    assert e.value.status == 6 and "column 3" in str(e.value)

@@ -1,0 +1,61 @@
+"""GPU FP32 path vs the FP64 oracle on the same seeded inputs (through the C ABI)."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import field_rel_err, oracle_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(cfgs, fields=None):
+    from paper_1601_00918_amd import Simulation
+    return Simulation(cfgs, fields=fields)
+
+
+@pytest.mark.parametrize("which", ["droplet", "poiseuille", "channel"])
+def test_initial_state_matches_oracle(gpu_available, which):
+    cfg = {"droplet": synth.config_droplet(n=64, r=10.0),
+           "poiseuille": synth.config_poiseuille(nx=64, width=32, wall_rows=8),
+           "channel": synth.config_channel(lam=64, theta=120.0, g=1e-5)}[which]
+    L, mask, rho0 = oracle_lattice(cfg)
+    sim = _sim([cfg])
+    assert np.array_equal(sim.fluid_mask(0), mask)
+    f = sim.populations(0)
+    # rounding of w_i rho0 to binary32 is the only difference
+    np.testing.assert_allclose(f, L.f, rtol=1e-7, atol=0)
+
+
+@pytest.mark.parametrize("which", ["droplet", "poiseuille", "channel"])
+def test_few_steps_populations(gpu_available, which):
+    cfg = {"droplet": synth.config_droplet(n=64, r=10.0),
+           "poiseuille": synth.config_poiseuille(nx=64, width=32, wall_rows=8),
+           "channel": synth.config_channel(lam=64, theta=120.0, g=1e-5)}[which]
+    L, mask, rho0 = oracle_lattice(cfg)
+    sim = _sim([cfg])
+    for n in (1, 2, 5):
+        L.step(n - L.t)
+        sim.step(n - sim.t)
+        f = sim.populations(0)
+        err = np.abs(f - L.f).max()
+        print(which, "t=%d max|df|=%.3e" % (n, err), flush=True)
+        assert err < 2e-7 * n
+
+
+@pytest.mark.parametrize("which", ["droplet", "poiseuille", "channel"])
+def test_moments_after_1000_steps(gpu_available, which):
+    cfg = {"droplet": synth.config_droplet(n=128, r=20.0),
+           "poiseuille": synth.config_poiseuille(),
+           "channel": synth.config_channel(lam=64, theta=120.0, g=1e-5)}[which]
+    L, mask, rho0 = oracle_lattice(cfg)
+    sim = _sim([cfg])
+    sim.step(1000)
+    L.step(1000)
+    ref = L.moments()
+    got = sim.moments(0)
+    erho = field_rel_err(ref["rho"], got["rho"], mask)
+    eu = field_rel_err(ref["u"], got["u"], mask)
+    ep = field_rel_err(ref["p"][None], got["p"][None], mask)
+    print(which, "rho", erho, "u", eu, "p", ep, flush=True)
+    assert max(erho) <= 1e-5
+    assert max(ep) <= 1e-5
