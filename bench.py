@@ -77,6 +77,29 @@ def cpu_baseline(seconds):
                       "%d steps in %.1f s" % (nf, n, dt)}
 
 
+def copy_calibration(steps, warmup, nbytes=2 << 30):
+    """A plain device-to-device copy of nbytes (torch's copy kernel): the
+    reference for the achievable HBM rate and for scaling the profiler's
+    FETCH_SIZE / WRITE_SIZE counters (it moves exactly 2 * nbytes per launch)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"workload": "copy", "bytes_per_launch": 2 * nbytes,
+                      "ms_per_copy": round(ms, 5),
+                      "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +118,9 @@ def main():
     import torch
     from paper_1601_00918_amd import Simulation
 
+    if args.workload == "copy":
+        copy_calibration(args.steps, args.warmup)
+        return
     cfgs, desc = workload(args.workload)
     nf = fluid_nodes(cfgs)
     sim = Simulation(cfgs, storage=args.storage)

@@ -184,6 +184,16 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, int32_t inst, double* f);
 /* Fluid mask the library uses for instance inst, host [ny][nx] (1 = fluid). */
 lbm_status lbm_fluid_mask(lbm_ctx* ctx, int32_t inst, uint8_t* mask);
 
+/*
+ * Tiling of the step kernel: every instance is cut into work items of bx
+ * consecutive columns (bx in {64, 128, 256}) by strip_rows rows (>= 4); one
+ * workgroup of bx threads advances one item.  Results do not depend on the
+ * tiling (bit for bit).  Synchronises the stream.
+ */
+lbm_status lbm_set_tiling(lbm_ctx* ctx, int32_t bx, int32_t strip_rows);
+lbm_status lbm_get_tiling(const lbm_ctx* ctx, int32_t* bx, int32_t* strip_rows,
+                          int32_t* n_items);
+
 /* Release the context (not the caller's workspace or stream). */
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -5,17 +5,19 @@ the computation runs in the HIP kernels of ``liblbm.so``.  PyTorch provides the
 device workspace and the stream.  Functions keep the ABI's names:
 
     lbm_required_bytes, lbm_init, lbm_step, lbm_time, lbm_set_fluid,
-    lbm_moments, lbm_monitors, lbm_get_populations, lbm_fluid_mask, lbm_destroy
+    lbm_moments, lbm_monitors, lbm_get_populations, lbm_fluid_mask, lbm_set_tiling,
+    lbm_get_tiling, lbm_destroy
 
 ``Simulation`` bundles a context with the torch workspace that backs it.
 """
 from .binding import (Simulation, geom_struct, fluid_struct, init_struct, lbm_destroy,
                       lbm_fluid_mask, lbm_get_populations, lbm_init, lbm_moments,
                       lbm_monitors, lbm_required_bytes, lbm_set_fluid, lbm_step, lbm_time,
-                      lbm_version)
+                      lbm_version, lbm_set_tiling, lbm_get_tiling)
 
 __all__ = [
     "Simulation", "geom_struct", "fluid_struct", "init_struct", "lbm_destroy",
     "lbm_fluid_mask", "lbm_get_populations", "lbm_init", "lbm_moments", "lbm_monitors",
     "lbm_required_bytes", "lbm_set_fluid", "lbm_step", "lbm_time", "lbm_version",
+    "lbm_set_tiling", "lbm_get_tiling",
 ]

@@ -21,7 +21,7 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 EXPORTED = [
     "lbm_last_error", "lbm_version", "lbm_required_bytes", "lbm_init", "lbm_step",
     "lbm_time", "lbm_set_fluid", "lbm_moments", "lbm_monitors", "lbm_get_populations",
-    "lbm_fluid_mask", "lbm_destroy",
+    "lbm_fluid_mask", "lbm_set_tiling", "lbm_get_tiling", "lbm_destroy",
 ]
 
 
@@ -82,6 +82,9 @@ def load():
     lib.lbm_monitors.argtypes = [vp, ctypes.POINTER(LbmMonitor)]
     lib.lbm_get_populations.argtypes = [vp, i32, dp]
     lib.lbm_fluid_mask.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint8)]
+    lib.lbm_set_tiling.argtypes = [vp, i32, i32]
+    lib.lbm_get_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     for name in EXPORTED:

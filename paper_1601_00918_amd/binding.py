@@ -155,6 +155,17 @@ def lbm_fluid_mask(ctx, inst, nx, ny):
     return m
 
 
+def lbm_set_tiling(ctx, bx, strip_rows):
+    check(_lib.load().lbm_set_tiling(ctx, int(bx), int(strip_rows)), "lbm_set_tiling")
+
+
+def lbm_get_tiling(ctx):
+    bx, st, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(_lib.load().lbm_get_tiling(ctx, ctypes.byref(bx), ctypes.byref(st), ctypes.byref(n)),
+          "lbm_get_tiling")
+    return bx.value, st.value, n.value
+
+
 def lbm_destroy(ctx):
     _lib.load().lbm_destroy(ctx)
 
@@ -221,6 +232,12 @@ class Simulation:
     def populations(self, inst=0):
         c = self.configs[inst]
         return lbm_get_populations(self.ctx, inst, c["nx"], c["ny"])
+
+    def set_tiling(self, bx, strip_rows):
+        lbm_set_tiling(self.ctx, bx, strip_rows)
+
+    def tiling(self):
+        return lbm_get_tiling(self.ctx)
 
     def fluid_mask(self, inst=0):
         c = self.configs[inst]

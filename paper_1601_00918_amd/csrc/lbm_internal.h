@@ -7,16 +7,17 @@
 
 namespace lbm {
 
-// One instance as the kernels see it.  Populations of species s, direction i
-// live at buf[f_off + (s * 9 + i) * plane + y * pitch + x] (x fastest).
+// One instance as the kernels see it.  The 18 population rows (species s,
+// direction i) of lattice row y are stored next to each other:
+//   buf[f_off + y * rstride + (s * 9 + i) * pitch + x],  rstride = 18 * pitch,
+// so one lattice row of one instance is a single contiguous block.
 struct InstDev {
     int64_t f_off;      // element offset of the instance in the population buffers
-    int64_t plane;      // elements per (species, direction) plane
     int32_t nx, ny;
-    int32_t pitch;      // elements per row (>= nx, multiple of 64)
+    int32_t pitch;      // elements per population row (>= nx, multiple of 64)
+    int32_t rstride;    // elements per lattice row (18 * pitch)
     int32_t periodic_y; // 1: box geometry, every node fluid, rows wrap
     int32_t col_off;    // offset of this instance's column table entries
-    int32_t pad0;
     float tau_h[2];     // tau^a - 1/2 (= nu^a / T0, Eqs. 4-5)
     float G36;          // G / 36: the D2Q9 weights of Eq. 8 are multiples of 1/36
     float rho_s[2];     // wall potentials
@@ -26,8 +27,9 @@ struct InstDev {
     double enc_ref[2];  // reserved for deviation storage
 };
 
-// A work item: one workgroup marches rows y0..y1-1 of the columns
-// x0..x0+BX-1 of instance inst.
+// A work item: one workgroup advances the columns x0..x0+BX-1 of instance
+// inst over rows y0..y1-1 marching up (y0 < y1), or over rows y0 down to
+// y1+1 marching down (y0 > y1).
 struct Item {
     int32_t inst, x0, y0, y1;
 };

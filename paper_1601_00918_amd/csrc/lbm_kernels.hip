@@ -12,7 +12,9 @@
 // fluid node.
 //
 // Tiling.  A workgroup of BX threads owns BX consecutive columns of one
-// instance and marches up a strip of rows y0..y1-1, one row per iteration.
+// instance and marches along a strip of rows, one row per iteration
+// (adjacent strips march in opposite directions, so the two workgroups that
+// both need a boundary row reach it at the same time and share it in L2).
 // The collision of row r needs the densities of rows r-1, r, r+1 at time t
 // (Eq. 8), so the march pulls row r+1, reduces it to its 12 moments (the
 // regularized collision depends on the populations only through rho, j and
@@ -93,92 +95,57 @@ struct ColG {
     Col m, c, p;  // columns x-1, x, x+1
 };
 
-// Pull the 18 populations f_i(x, r, t) of a fluid node (Eq. 1 with half-way
-// bounce-back).  xm/xp are the wrapped neighbour columns.
-__device__ __forceinline__ void pull_node(const float* __restrict__ fin, const InstDev& P,
-                                          int xm, int x, int xp, int r, const ColG& g,
-                                          float (&f)[2][9])
-{
-    const float* base = fin + P.f_off;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int sx = kCx[i] == 1 ? xm : (kCx[i] == -1 ? xp : x);
-        int sy = r - kCy[i];
-        bool src_fluid;
-        if (P.periodic_y) {
-            sy = wrapi(sy, P.ny);
-            src_fluid = true;
-        } else {
-            const Col cc = kCx[i] == 1 ? g.m : (kCx[i] == -1 ? g.p : g.c);
-            src_fluid = in_run(cc, sy);
-        }
-        const int64_t off = src_fluid ? (int64_t)sy * P.pitch + sx : (int64_t)r * P.pitch + x;
-        const int dir = src_fluid ? i : kOpp[i];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            f[s][i] = base[(int64_t)(s * 9 + dir) * P.plane + off];
-    }
-}
-
-// One population of node (x, r) for a lane-varying direction i.
-__device__ __forceinline__ float pull_one(const float* __restrict__ fin, const InstDev& P, int s,
-                                          int i, int xm, int x, int xp, int r, const ColG& g)
-{
-    const int cx = dir_cx(i), cy = dir_cy(i);
-    const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
-    int sy = r - cy;
-    bool src_fluid;
-    if (P.periodic_y) {
-        sy = wrapi(sy, P.ny);
-        src_fluid = true;
-    } else {
-        const Col cc = cx == 1 ? g.m : (cx == -1 ? g.p : g.c);
-        src_fluid = in_run(cc, sy);
-    }
-    const int64_t off = src_fluid ? (int64_t)sy * P.pitch + sx : (int64_t)r * P.pitch + x;
-    const int dir = src_fluid ? i : dir_opp(i);
-    return fin[P.f_off + (int64_t)(s * 9 + dir) * P.plane + off];
-}
-
 // Post-collision populations of one species (Eqs. 3, 6, 7, 9) in FP32.
 //   m      moments of the pulled populations
 //   vx,vy  shifted equilibrium velocity u_mix + F / rho (Eqs. 9-10)
 //   om     1 - 1 / tau_mix
-// The equilibrium is written as w_i rho (1 + P_i(v)); w_i rho is formed as
-// (36 w_i) * (rho / 36) with a correctly rounded division, so the nine rest
-// parts sum to the same value for every direction set and carry no bias.
-// The regularized non-equilibrium part is the second-order Hermite
+// Equilibrium: f_i^eq = w_i rho (1 + P(c_i . v)) with, for T0 = 1/3 and
+// cu = c_i . v, P = E + O, E = 4.5 cu^2 - 1.5 v^2 (even in cu) and
+// O = cu (3 - 4.5 v^2 + 4.5 cu^2) (odd in cu), so the two directions of a pair
+// (c_i, -c_i) share E and take +-O.  The rest parts w_i rho are exact
+// multiples (16, 4, 1) of one correctly rounded rho / 36: every direction
+// carries the same unbiased relative rounding, so neither the mass nor the
+// momentum of the equilibrium drifts (a rounded constant weight such as
+// fl(1/9) would scale the momentum by a fixed factor every step).
+// Regularized non-equilibrium part (Eq. 6): the second-order Hermite
 // projection w_i / (2 T0^2) H_i : Pi^neq of the species' non-equilibrium
 // momentum flux Pi^neq = Pi - rho T0 I - j j / rho, the second moment of
-// f - f^eq(rho, j / rho) in closed form (the species' own equilibrium).
+// f - f^eq(rho, j / rho) in closed form (the species' own equilibrium); on
+// D2Q9 it takes five distinct values (rest, axis x, axis y, two diagonals).
 __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy, float om,
                                                 float (&out)[9])
 {
-    const float third = 1.0f / 3.0f;
-    const float ax = m.jx / m.rho, ay = m.jy / m.rho;
-    const float nxx = m.pxx - (m.rho * third + m.jx * ax);
-    const float nyy = m.pyy - (m.rho * third + m.jy * ay);
+    const float rinv = __builtin_amdgcn_rcpf(m.rho);
+    const float ax = m.jx * rinv, ay = m.jy * rinv;
+    const float nxx = m.pxx - (m.rho * (1.0f / 3.0f) + m.jx * ax);
+    const float nyy = m.pyy - (m.rho * (1.0f / 3.0f) + m.jy * ay);
     const float nxy = m.pxy - m.jx * ay;
     const float tr = nxx + nyy;
-    float fneq[9];
-    fneq[0] = -(2.0f / 3.0f) * tr;
-    fneq[1] = (2.0f * nxx - nyy) * (1.0f / 6.0f);
-    fneq[3] = fneq[1];
-    fneq[2] = (2.0f * nyy - nxx) * (1.0f / 6.0f);
-    fneq[4] = fneq[2];
-    fneq[5] = tr * (1.0f / 12.0f) + 0.25f * nxy;
-    fneq[7] = fneq[5];
-    fneq[6] = tr * (1.0f / 12.0f) - 0.25f * nxy;
-    fneq[8] = fneq[6];
-    const float r36 = m.rho / 36.0f;
-    const float usq15 = 1.5f * (vx * vx + vy * vy);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const float base = kW36[i] * r36;
-        const float cu = kCx[i] * vx + kCy[i] * vy;
-        const float poly = 3.0f * cu * (1.0f + 1.5f * cu * (1.0f + cu) - usq15) - usq15;
-        out[i] = base + (base * poly + om * fneq[i]);
-    }
+    const float g0 = om * (-(2.0f / 3.0f) * tr);
+    const float g1 = om * ((2.0f * nxx - nyy) * (1.0f / 6.0f));
+    const float g2 = om * ((2.0f * nyy - nxx) * (1.0f / 6.0f));
+    const float gd = tr * (1.0f / 12.0f);
+    const float g5 = om * (gd + 0.25f * nxy);
+    const float g6 = om * (gd - 0.25f * nxy);
+    const float b5 = m.rho / 36.0f;  // correctly rounded: no bias in w_i rho
+    const float b1 = 4.0f * b5;
+    const float b0 = 16.0f * b5;
+    const float vsq15 = 1.5f * (vx * vx + vy * vy);
+    const float t = 3.0f - 3.0f * vsq15;
+    out[0] = b0 + (g0 - b0 * vsq15);
+    auto pair = [&](float cu, float b, float g, float& plus, float& minus) {
+        const float cu2 = cu * cu;
+        const float E = 4.5f * cu2 - vsq15;
+        const float O = cu * (t + 4.5f * cu2);
+        const float C = b + (b * E + g);
+        const float BO = b * O;
+        plus = C + BO;
+        minus = C - BO;
+    };
+    pair(vx, b1, g1, out[1], out[3]);
+    pair(vy, b1, g2, out[2], out[4]);
+    pair(vx + vy, b5, g5, out[5], out[7]);
+    pair(vy - vx, b5, g6, out[6], out[8]);
 }
 
 __device__ __forceinline__ int remap_xcd(int b, int n)
@@ -191,41 +158,76 @@ __device__ __forceinline__ int remap_xcd(int b, int n)
     return start + slot;
 }
 
-template <int BX, int MODE>
-__global__ void __launch_bounds__(BX)
-step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
-            const InstDev* __restrict__ insts, const Item* __restrict__ items, int item_base,
-            const Col* __restrict__ cols, double* __restrict__ partial,
-            double* __restrict__ stage)
+// Barrier that orders LDS only: global loads of the next row stay in flight.
+__device__ __forceinline__ void lds_barrier()
 {
-    __shared__ float ring[4][2][BX + 2];
-    __shared__ double red[BX / 64][kMonWidth];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
-    const int item_idx = item_base + remap_xcd((int)blockIdx.x, (int)gridDim.x);
-    const Item it = items[item_idx];
-    const InstDev P = insts[it.inst];
+// Byte offsets (relative to the instance's first element) of the 9 pulled
+// populations of species 0 at node (x, r); species 1 adds 9 * pitch elements.
+// rb[k] is the element offset (row index times rstride) of row r - 1 + k.
+// Where x - c_i is solid the half-way bounce-back source f*_opp(i)(x) is used
+// instead.  Instances are smaller than 4 GiB, so 32-bit offsets suffice.
+template <bool PY>
+__device__ __forceinline__ void pull_offsets(const InstDev& P, const int (&rb)[3], int r, int xm,
+                                             int x, int xp, const ColG& g, uint32_t (&off)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int cx = kCx[i], cy = kCy[i];
+        const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
+        const int srb = rb[1 - cy];
+        bool src_fluid = true;
+        if (!PY) {
+            const Col cc = cx == 1 ? g.m : (cx == -1 ? g.p : g.c);
+            const int sy = r - cy;
+            src_fluid = (sy >= cc.lo) & (sy <= cc.hi);
+        }
+        const uint32_t o_src = 4u * ((uint32_t)(i * P.pitch) + (uint32_t)(srb + sx));
+        const uint32_t o_bb = 4u * ((uint32_t)(kOpp[i] * P.pitch) + (uint32_t)(rb[1] + x));
+        off[i] = src_fluid ? o_src : o_bb;
+    }
+}
+
+template <int BX, int MODE, bool PY>
+__device__ __forceinline__ void march(const float* __restrict__ fin, float* __restrict__ fout,
+                                      const InstDev& P, const Item& it, int item_idx,
+                                      const Col* __restrict__ cols, double* __restrict__ partial,
+                                      double* __restrict__ stage, float (&ring)[4][2][BX + 2],
+                                      double (&red)[BX / 64][kMonWidth])
+{
     const int tid = threadIdx.x;
     const int wdt = min(BX, P.nx - it.x0);
     const bool act = tid < wdt;
     const int x = it.x0 + (act ? tid : 0);
     const int xm = wrapi(x - 1, P.nx), xp = wrapi(x + 1, P.nx);
-    ColG g;
-    if (!P.periodic_y) {
+    // Scalar base pointers; every lane adds a 32-bit byte offset.
+    const char* __restrict__ base0 = reinterpret_cast<const char*>(fin + P.f_off);
+    const char* __restrict__ base1 = base0 + 36 * P.pitch;  // species 1
+    char* __restrict__ obase = reinterpret_cast<char*>(fout + P.f_off);
+    const uint32_t sp = 36u * (uint32_t)P.pitch;  // species stride in bytes
+    ColG g{};
+    if (!PY) {
         g.m = cols[P.col_off + xm];
         g.c = cols[P.col_off + x];
         g.p = cols[P.col_off + xp];
     }
-
-    // Halo lanes (wave 0): lane 16 k + j, k = side * 2 + species, j = direction.
+    // Halo lanes of wave 0: lane 16 k + j, k = side * 2 + species, j = direction.
     const int hk = (tid >> 4) & 3, hj = tid & 15;
     const int hside = hk >> 1, hs = hk & 1;
+    const bool hlane = tid < 64 && hj < 9;
     const int hx = hside ? wrapi(it.x0 + wdt, P.nx) : wrapi(it.x0 - 1, P.nx);
     const int hxm = wrapi(hx - 1, P.nx), hxp = wrapi(hx + 1, P.nx);
-    ColG hg;
-    if (tid < 64 && !P.periodic_y) {
-        hg.m = cols[P.col_off + hxm];
-        hg.c = cols[P.col_off + hx];
-        hg.p = cols[P.col_off + hxp];
+    const int hd = hj < 9 ? hj : 0;
+    const int hcx = dir_cx(hd), hcy = dir_cy(hd), hopp = dir_opp(hd);
+    const int hsx = hcx == 1 ? hxm : (hcx == -1 ? hxp : hx);
+    Col hgc{0, 0}, hgs{0, 0};
+    if (!PY && tid < 64) {
+        hgc = cols[P.col_off + hx];
+        hgs = cols[P.col_off + hsx];
     }
 
     const int64_t n_nodes = (int64_t)P.nx * P.ny;
@@ -234,28 +236,65 @@ step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
     for (int j = 0; j < kMonWidth; ++j)
         macc[j] = 0.0;
     double cosx = 0.0, sinx = 0.0;
-    if (MODE != kStep)
+    if (MODE == kStepMon || MODE == kMonOnly)
         sincospi(2.0 * (double)x / (double)P.nx, &sinx, &cosx);
 
+    auto row_of = [&](int r) -> int { return PY ? wrapi(r, P.ny) : r; };
+    auto node_fluid = [&](const Col& c, int rr) -> bool {
+        return PY ? true : ((rr >= c.lo) & (rr <= c.hi));
+    };
+
+    // Issue the pulls of row r into raw / hraw (loads left in flight).
+    float raw[18];
+    float hraw = 0.0f;
+    bool fl_next = false, hfl_next = false;
+    auto issue_row = [&](int r) {
+        const int rr = row_of(r);
+        int rb[3];
+        rb[0] = row_of(r - 1) * P.rstride;
+        rb[1] = rr * P.rstride;
+        rb[2] = row_of(r + 1) * P.rstride;
+        fl_next = act && node_fluid(g.c, rr);
+        if (fl_next) {
+            uint32_t off[9];
+            pull_offsets<PY>(P, rb, rr, xm, x, xp, g, off);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                raw[i] = *reinterpret_cast<const float*>(base0 + off[i]);
+                raw[9 + i] = *reinterpret_cast<const float*>(base1 + off[i]);
+            }
+        }
+        hfl_next = node_fluid(hgc, rr);
+        if (hlane && hfl_next) {
+            const int srb = rb[1 - hcy];
+            const bool src_fluid = PY ? true : (((rr - hcy) >= hgs.lo) & ((rr - hcy) <= hgs.hi));
+            const uint32_t o = src_fluid ? 4u * ((uint32_t)(hd * P.pitch) + (uint32_t)(srb + hsx))
+                                         : 4u * ((uint32_t)(hopp * P.pitch) + (uint32_t)(rb[1] + hx));
+            hraw = *reinterpret_cast<const float*>(base0 + o + (hs ? sp : 0u));
+        }
+    };
+
+    // March direction: y0 < y1 marches up over rows y0 .. y1 - 1; y0 > y1
+    // marches down over rows y0 .. y1 + 1.  Row r is pulled in the iteration
+    // that collides row r - d.
+    const int d = it.y1 > it.y0 ? 1 : -1;
     Mom prev[2], cur[2];
     bool prev_fluid = false;
+    issue_row(it.y0 - d);
 
-    for (int r = it.y0 - 1; r <= it.y1; ++r) {
-        const int rr = P.periodic_y ? wrapi(r, P.ny) : r;
-        // ---- phase 1: pull row r and publish its densities ----------------
-        const bool fl = act && (P.periodic_y || in_run(g.c, rr));
+    for (int r = it.y0 - d; r != it.y1 + d; r += d) {
+        const int rr = row_of(r);
+        // ---- row r: moments from the pulls issued one iteration earlier ----
+        const bool fl = fl_next;
+        const bool hfl = hfl_next;
         if (fl) {
-            float f[2][9];
-            pull_node(fin, P, xm, x, xp, rr, g, f);
-            cur[0] = moments9(f[0]);
-            cur[1] = moments9(f[1]);
-            if (MODE == kExport && r >= it.y0 && r < it.y1) {
+            cur[0] = moments9(raw);
+            cur[1] = moments9(raw + 9);
+            if (MODE == kExport && d * (r - it.y0) >= 0 && d * (it.y1 - r) > 0) {
                 const int64_t k = (int64_t)rr * P.nx + x;
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        stage[(int64_t)(s * 9 + i) * n_nodes + k] = (double)f[s][i];
+                for (int i = 0; i < 18; ++i)
+                    stage[(int64_t)i * n_nodes + k] = (double)raw[i];
             }
         }
         if (act) {
@@ -263,25 +302,26 @@ step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
             ring[r & 3][1][tid + 1] = fl ? cur[1].rho : P.rho_s[1];
         }
         if (tid < 64) {
-            const bool hfl = P.periodic_y || in_run(hg.c, rr);
-            float v = 0.0f;
-            if (hfl && hj < 9)
-                v = pull_one(fin, P, hs, hj, hxm, hx, hxp, rr, hg);
+            const float v = (hlane && hfl) ? hraw : 0.0f;
             float q[9];
 #pragma unroll
             for (int j = 0; j < 9; ++j)
                 q[j] = __shfl(v, (tid & ~15) + j, 64);
             const float rh = rho9(q);
             if (hj == 0)
-                ring[r & 3][hs][hside ? wdt + 1 : 0] = hfl ? rh : (hs ? P.rho_s[1] : P.rho_s[0]);
+                ring[r & 3][hs][hside ? wdt + 1 : 0] =
+                    hfl ? rh : (hs ? P.rho_s[1] : P.rho_s[0]);
         }
-        __syncthreads();
+        // ---- pulls of row r + d go out before the barrier -----------------
+        if (r != it.y1)
+            issue_row(r + d);
+        lds_barrier();
 
-        // ---- phase 2: collide row r - 1 ---------------------------------
-        if (r - 1 >= it.y0 && prev_fluid) {
-            const int rc = r - 1;
-            const int rrc = P.periodic_y ? wrapi(rc, P.ny) : rc;
-            const int rs = (rc - 1) & 3, rm = rc & 3, rn = r & 3;
+        // ---- collide row r - d ---------------------------------------------
+        if (d * (r - d - it.y0) >= 0 && prev_fluid) {
+            const int rc = r - d;
+            const int rrc = row_of(rc);
+            const int rs = (rc - 1) & 3, rm = rc & 3, rn = (rc + 1) & 3;
             float sx[2], sy[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -295,15 +335,14 @@ step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
             }
             const float ro = prev[0].rho, rw = prev[1].rho;
             const float rho = ro + rw;
-            const float inv = 1.0f / rho;
+            const float inv = 1.0f / rho;  // correctly rounded: u_mix carries no bias
             const float ux = (prev[0].jx + prev[1].jx) * inv;
             const float uy = (prev[0].jy + prev[1].jy) * inv;
             const float taum = 0.5f + (ro * P.tau_h[0] + rw * P.tau_h[1]) * inv;
-            const float om = 1.0f - 1.0f / taum;
+            const float om = 1.0f - __builtin_amdgcn_rcpf(taum);
 
             if (MODE == kStep || MODE == kStepMon) {
-                const int64_t off = (int64_t)rrc * P.pitch + x;
-                float* ob = fout + P.f_off;
+                const uint32_t o = 4u * (uint32_t)(rrc * P.rstride + x);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const float vx = ux + P.G36 * sx[s] + P.g[0];
@@ -311,8 +350,12 @@ step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
                     float out[9];
                     collide_species(prev[s], vx, vy, om, out);
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        ob[(int64_t)(s * 9 + i) * P.plane + off] = out[i];
+                    for (int i = 0; i < 9; ++i) {
+                        // Streaming store: the populations are read back only by
+                        // the next step, long after they would have left L2.
+                        char* dst = obase + 4 * (s * 9 + i) * P.pitch;
+                        __builtin_nontemporal_store(out[i], reinterpret_cast<float*>(dst + o));
+                    }
                 }
             }
             if (MODE != kStep) {
@@ -371,6 +414,24 @@ step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
             partial[(int64_t)item_idx * kMonWidth + tid] = v;
         }
     }
+}
+
+template <int BX, int MODE>
+__global__ void __launch_bounds__(BX)
+step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
+            const InstDev* __restrict__ insts, const Item* __restrict__ items, int item_base,
+            const Col* __restrict__ cols, double* __restrict__ partial,
+            double* __restrict__ stage)
+{
+    __shared__ float ring[4][2][BX + 2];
+    __shared__ double red[BX / 64][kMonWidth];
+    const int item_idx = item_base + remap_xcd((int)blockIdx.x, (int)gridDim.x);
+    const Item it = items[item_idx];
+    const InstDev P = insts[it.inst];
+    if (P.periodic_y)
+        march<BX, MODE, true>(fin, fout, P, it, item_idx, cols, partial, stage, ring, red);
+    else
+        march<BX, MODE, false>(fin, fout, P, it, item_idx, cols, partial, stage, ring, red);
 }
 
 __global__ void mon_reduce_kernel(const double* __restrict__ partial,
@@ -456,7 +517,7 @@ __global__ void init_kernel(float* __restrict__ A, const InstDev* __restrict__ i
         }
         for (int s = 0; s < 2; ++s) {
             const double rho0 = init_density(ini, P, s, xr, yr);
-            A[P.f_off + (int64_t)(s * 9 + i) * P.plane + (int64_t)y * P.pitch + x] =
+            A[P.f_off + (int64_t)y * P.rstride + (int64_t)(s * 9 + i) * P.pitch + x] =
                 (float)(w * rho0);
         }
     }

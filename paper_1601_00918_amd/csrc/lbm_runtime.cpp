@@ -41,7 +41,7 @@ lbm_status fail(lbm_status st, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int kMinBx = 64;
-constexpr int kMinStrip = 8;
+constexpr int kMinStrip = 4;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -50,7 +50,7 @@ struct InstHost {
     int kind;
     int nx, ny;
     int pitch;
-    int64_t plane;
+    int64_t elems;  // population elements of this instance (18 * pitch * ny, padded)
     int64_t f_off;
     std::vector<Col> cols;  // per column fluid run
 };
@@ -108,6 +108,10 @@ lbm_status check_geom(const lbm_geom& g)
 {
     if (g.nx < 1 || g.ny < 1 || g.nx > 32768 || g.ny > 32768)
         return fail(LBM_ERR_INVALID, "geometry size %d x %d out of range", g.nx, g.ny);
+    // The kernels address an instance with 32-bit byte offsets.
+    if ((int64_t)72 * (int64_t)((g.nx + 63) / 64 * 64) * g.ny >= ((int64_t)1 << 32))
+        return fail(LBM_ERR_UNSUPPORTED,
+                    "instance %d x %d too large (its populations exceed 4 GiB)", g.nx, g.ny);
     if (g.kind == LBM_GEOM_BOX) {
         if (g.ny < 3 || g.nx < 3)
             return fail(LBM_ERR_INVALID, "box geometry needs nx, ny >= 3");
@@ -147,7 +151,8 @@ lbm_status check_fluid(const lbm_fluid& f)
 
 int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
 
-int64_t plane_of(int nx, int ny) { return (int64_t)align_up((size_t)pitch_of(nx) * ny, 64); }
+// Elements of one instance in one population buffer.
+int64_t inst_elems(int nx, int ny) { return (int64_t)18 * pitch_of(nx) * ny; }
 
 size_t elem_size(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
@@ -173,7 +178,7 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage)
     L.max_nodes = 0;
     for (int k = 0; k < n_inst; ++k) {
         const lbm_geom& g = geoms[k];
-        elems += 18 * plane_of(g.nx, g.ny);
+        elems += inst_elems(g.nx, g.ny);
         ncols += g.nx;
         L.n_items_max += max_items(g);
         L.max_nodes = std::max<int64_t>(L.max_nodes, (int64_t)g.nx * g.ny);
@@ -246,7 +251,9 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
 }
 
 // Cut every instance into work items: blocks of bx columns, each split into
-// strips of `strip` rows covering the block's fluid rows.
+// strips of `strip` rows covering the block's fluid rows.  Items are ordered
+// strip-major (all column blocks of one band of rows, then the next band), so
+// the blocks that share boundary cache lines run side by side on one XCD.
 void build_items(lbm_ctx* c)
 {
     c->items.clear();
@@ -255,18 +262,31 @@ void build_items(lbm_ctx* c)
     for (int k = 0; k < c->n_inst; ++k) {
         const InstHost& h = c->ih[k];
         c->item_first[k] = (int32_t)c->items.size();
-        for (int x0 = 0; x0 < h.nx; x0 += c->bx) {
-            const int x1 = std::min(h.nx, x0 + c->bx);
-            int ylo = h.ny, yhi = -1;
-            for (int x = x0; x < x1; ++x)
+        const int nblk = (h.nx + c->bx - 1) / c->bx;
+        std::vector<int> ylo(nblk, h.ny), yhi(nblk, -1);
+        int glo = h.ny, ghi = -1;
+        for (int b = 0; b < nblk; ++b) {
+            for (int x = b * c->bx; x < std::min(h.nx, (b + 1) * c->bx); ++x)
                 if (h.cols[x].lo <= h.cols[x].hi) {
-                    ylo = std::min(ylo, h.cols[x].lo);
-                    yhi = std::max(yhi, h.cols[x].hi);
+                    ylo[b] = std::min(ylo[b], h.cols[x].lo);
+                    yhi[b] = std::max(yhi[b], h.cols[x].hi);
                 }
-            if (yhi < ylo)
-                continue;
-            for (int y0 = ylo; y0 <= yhi; y0 += c->strip)
-                c->items.push_back(Item{k, x0, y0, std::min(yhi + 1, y0 + c->strip)});
+            glo = std::min(glo, ylo[b]);
+            ghi = std::max(ghi, yhi[b]);
+        }
+        int band = 0;
+        for (int y0 = glo; y0 <= ghi; y0 += c->strip, ++band) {
+            const int y1 = std::min(ghi + 1, y0 + c->strip);
+            for (int b = 0; b < nblk; ++b) {
+                const int a0 = std::max(y0, ylo[b]), a1 = std::min(y1, yhi[b] + 1);
+                if (a0 >= a1)
+                    continue;
+                // odd bands march down: rows a1 - 1 .. a0
+                if (band & 1)
+                    c->items.push_back(Item{k, b * c->bx, a1 - 1, a0 - 1});
+                else
+                    c->items.push_back(Item{k, b * c->bx, a0, a1});
+            }
         }
         c->item_count[k] = (int32_t)c->items.size() - c->item_first[k];
     }
@@ -393,14 +413,14 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         h.nx = g.nx;
         h.ny = g.ny;
         h.pitch = pitch_of(g.nx);
-        h.plane = plane_of(g.nx, g.ny);
+        h.elems = inst_elems(g.nx, g.ny);
         h.f_off = f_off;
-        f_off += 18 * h.plane;
+        f_off += h.elems;
         max_nx = std::max(max_nx, g.nx);
         InstDev& d = c->idv[k];
         std::memset(&d, 0, sizeof d);
         d.f_off = h.f_off;
-        d.plane = h.plane;
+        d.rstride = 18 * h.pitch;
         d.nx = g.nx;
         d.ny = g.ny;
         d.pitch = h.pitch;
@@ -409,9 +429,11 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         fill_inst_params(d, fluids[k]);
         all_cols.insert(all_cols.end(), h.cols.begin(), h.cols.end());
     }
-    // Default tiling: widest block not wider than the widest instance.
+    // Default tiling: widest block not wider than the widest instance, short
+    // strips (many concurrent items sweeping a narrow band of rows, so halo
+    // rows and block-boundary lines are shared in L2).
     c->bx = max_nx >= 256 ? 256 : (max_nx >= 128 ? 128 : 64);
-    c->strip = 32;
+    c->strip = 8;
     build_items(c);
 
     lbm_status st = LBM_OK;
@@ -576,6 +598,34 @@ lbm_status lbm_fluid_mask(lbm_ctx* c, int32_t inst, uint8_t* mask)
     for (int y = 0; y < h.ny; ++y)
         for (int x = 0; x < h.nx; ++x)
             mask[(size_t)y * h.nx + x] = (y >= h.cols[x].lo && y <= h.cols[x].hi) ? 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tiling(lbm_ctx* c, int32_t bx, int32_t strip_rows)
+{
+    if (!c)
+        return fail(LBM_ERR_INVALID, "lbm_set_tiling: null context");
+    if (bx != 64 && bx != 128 && bx != 256)
+        return fail(LBM_ERR_INVALID, "lbm_set_tiling: bx must be 64, 128 or 256");
+    if (strip_rows < kMinStrip || strip_rows > 32768)
+        return fail(LBM_ERR_INVALID, "lbm_set_tiling: strip_rows must be >= %d", kMinStrip);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->bx = bx;
+    c->strip = strip_rows;
+    build_items(c);
+    return upload_tables(c);
+}
+
+lbm_status lbm_get_tiling(const lbm_ctx* c, int32_t* bx, int32_t* strip_rows, int32_t* n_items)
+{
+    if (!c)
+        return fail(LBM_ERR_INVALID, "lbm_get_tiling: null context");
+    if (bx)
+        *bx = c->bx;
+    if (strip_rows)
+        *strip_rows = c->strip;
+    if (n_items)
+        *n_items = (int32_t)c->items.size();
     return LBM_OK;
 }
 
