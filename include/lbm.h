@@ -109,11 +109,14 @@ typedef struct {
     const double* rho0;  /* FIELD (reserved), [2][ny][nx] */
 } lbm_init_fields;
 
-/* Population storage format in HBM (arithmetic is always FP32). */
+/* Population storage format in HBM (arithmetic is always FP32).  The storage
+ * argument of lbm_required_bytes / lbm_init may be OR-ed with LBM_OPT_SNAPSHOT
+ * to reserve a snapshot buffer (lbm_snapshot_save / lbm_snapshot_restore). */
 typedef enum {
     LBM_STORE_F32 = 0,
     LBM_STORE_F16 = 1,   /* reserved: FP16 deviation storage */
-    LBM_STORE_BF16 = 2   /* reserved: BF16 deviation storage */
+    LBM_STORE_BF16 = 2,  /* reserved: BF16 deviation storage */
+    LBM_OPT_SNAPSHOT = 0x100
 } lbm_storage;
 
 /* Per-instance monitor values, accumulated in FP64 over fluid nodes at the
@@ -152,9 +155,21 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
                     void* device_workspace, size_t workspace_bytes, void* hip_stream,
                     lbm_ctx** out);
 
-/* Advance every instance by nsteps time steps (Eq. 1).  Enqueues work and
- * returns without synchronising. */
+/* Advance every active instance by nsteps time steps (Eq. 1).  Enqueues work
+ * and returns without synchronising.  On a non-null stream, runs of 64 steps are
+ * replayed from a captured HIP graph (same kernels, same results). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Choose which instances lbm_step advances: active[n_inst], nonzero = advance.
+ * Inactive instances keep their state; monitors and exports still cover them.
+ * Synchronises the stream. */
+lbm_status lbm_set_active(lbm_ctx* ctx, const uint8_t* active);
+
+/* Copy the whole current state into the snapshot buffer (needs
+ * LBM_OPT_SNAPSHOT at init), or copy instance inst (all instances if inst < 0)
+ * back from it.  Stream-ordered; no synchronisation. */
+lbm_status lbm_snapshot_save(lbm_ctx* ctx);
+lbm_status lbm_snapshot_restore(lbm_ctx* ctx, int32_t inst);
 
 /* Current time step count. */
 int64_t lbm_time(const lbm_ctx* ctx);
@@ -196,6 +211,104 @@ lbm_status lbm_get_tiling(const lbm_ctx* ctx, int32_t* bx, int32_t* strip_rows,
 
 /* Release the context (not the caller's workspace or stream). */
 void lbm_destroy(lbm_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Critical pressure (Sec. 3.4): the smallest homogeneous body acceleration g
+ * (along +x) that mobilises an oil slug, found by bisection in log g over
+ * independent runs ("probes") that each restart from an equilibrated state.
+ *
+ * A probe at g advances the slug in chunks and watches its periodic centre of
+ * oil mass X (unwrapped displacement since the probe started) and mean oil
+ * velocity U = sum rho^o u_x / sum rho^o:
+ *   moving  once X >= move_frac * lambda;
+ *   static  once at least min_steps have run, |U| < still_frac * U_ref for
+ *           still_chunks consecutive chunks and X < creep_frac * lambda, with
+ *           U_ref = g h0^2 / (3 nu_w) and nu_w = (tau_w - 1/2) / 3;
+ *   at the step budget: moving if X >= creep_frac * lambda, else static
+ *           (LBM_CP_UNDECIDED is set);
+ *   a non-finite or non-positive density counts as moving (LBM_CP_UNSTABLE).
+ * Moving shrinks the bracket from above, static from below; the solve stops
+ * when (g_hi - g_lo) / g_lo <= rel_tol and reports g_crit = sqrt(g_lo g_hi)
+ * and Bo = rho_bar g_crit L D / sigma (Eq. 15) with L = nx and D = h0 - a.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    lbm_geom geom;          /* LBM_GEOM_CHANNEL */
+    lbm_fluid fluid;        /* tau, G, rho_s; g is set by the solver */
+    lbm_init_fields init;   /* usually LBM_INIT_SLUG */
+    double sigma;           /* surface tension used for Bo */
+    double rho_bar;         /* density used for Bo */
+    double g_lo, g_hi;      /* initial bracket, 0 < g_lo < g_hi */
+    int64_t equil_steps;    /* unforced steps before the snapshot */
+    int64_t max_steps;      /* step budget of one probe */
+} lbm_cp_problem;
+
+typedef struct {
+    double rel_tol;         /* default 0.005 */
+    double move_frac;       /* default 0.5 */
+    double creep_frac;      /* default 0.25 */
+    double still_frac;      /* default 1e-3 */
+    int32_t chunk_steps;    /* steps between monitor checks, default 1000 (even) */
+    int32_t still_chunks;   /* default 3 */
+    int32_t max_probes;     /* default 60 */
+    int32_t verify_bracket; /* 1: probe both ends first and widen the bracket
+                               (by a factor 10^0.5 per try) until g_lo is static and
+                               g_hi is moving */
+    int64_t min_steps;      /* default 20000 */
+} lbm_cp_options;
+
+enum {
+    LBM_CP_UNDECIDED = 1,   /* a probe hit its step budget */
+    LBM_CP_UNSTABLE = 2,    /* a probe became non-physical */
+    LBM_CP_WIDENED = 4,     /* the initial bracket had to be widened */
+    LBM_CP_NOT_CONVERGED = 8 /* max_probes reached before rel_tol */
+};
+
+typedef struct {
+    double g_lo, g_hi;      /* final bracket */
+    double g_crit;          /* sqrt(g_lo g_hi) */
+    double bo_crit;         /* Eq. 15 */
+    int32_t probes;         /* probes run */
+    int32_t flags;          /* LBM_CP_* */
+    int64_t steps;          /* lattice steps run (equilibration included) */
+} lbm_cp_result;
+
+/* Fill opts with the defaults above. */
+void lbm_cp_default_options(lbm_cp_options* opts);
+
+/* Workspace bytes lbm_critical_pressure needs for these problems. */
+lbm_status lbm_cp_required_bytes(const lbm_cp_problem* probs, int32_t n, size_t* bytes);
+
+/*
+ * Solve n critical-pressure problems together on the GPU: all problems are
+ * equilibrated and probed in one batched launch per step; a problem whose
+ * probe ends restarts at once from its snapshot with the next g, and finished
+ * problems leave the launch.  results[n] is caller-owned.  Synchronises.
+ */
+lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
+                                 const lbm_cp_options* opts, void* device_workspace,
+                                 size_t workspace_bytes, void* hip_stream,
+                                 lbm_cp_result* results);
+
+/*
+ * The same bisection and classification driven through caller callbacks (for
+ * other engines and for testing the driver itself).  The driver calls
+ *   begin_probe(user, k, g)        restart problem k from its equilibrated state
+ *                                   with body acceleration g;
+ *   advance(user, active, steps)   advance the problems with active[k] != 0;
+ *   monitors(user, mon)            monitors of all n problems at the current time.
+ * Each callback returns 0 on success.  probs supplies geometry (lambda, h0, a,
+ * nx), tau_w, sigma, rho_bar, the bracket and the step budget; equil_steps is
+ * ignored (the engine starts equilibrated).
+ */
+typedef struct {
+    int (*begin_probe)(void* user, int32_t k, double g);
+    int (*advance)(void* user, const uint8_t* active, int64_t steps);
+    int (*monitors)(void* user, lbm_monitor* mon);
+    void* user;
+} lbm_cp_engine;
+
+lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs, int32_t n,
+                        const lbm_cp_options* opts, lbm_cp_result* results);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,174 @@
+"""Critical-pressure search on the oracle (Sec. 3.4): the smallest body
+acceleration that mobilises the slug, by bisection in log g over probes that
+restart from an equilibrated state.
+
+TEST INFRASTRUCTURE (see the package docstring).  This is an independent
+implementation of the probe rules the library documents (moving once the
+slug's centre of oil mass has advanced by move_frac * lambda; static once
+min_steps have run, the mean oil velocity has stayed below still_frac * U_ref
+for still_chunks consecutive checks and the slug has advanced less than
+creep_frac * lambda, U_ref = g h0^2 / (3 nu_w); at the step budget, moving iff it
+advanced creep_frac * lambda; a non-physical state counts as moving; stop when
+(g_hi - g_lo) / g_lo <= rel_tol).  It shares no code with the library.
+"""
+import math
+
+import numpy as np
+
+UNDECIDED, UNSTABLE, WIDENED, NOT_CONVERGED = 1, 2, 4, 8
+
+DEFAULT_RULES = dict(rel_tol=0.005, move_frac=0.5, creep_frac=0.25, still_frac=1e-3,
+                     chunk_steps=1000, still_chunks=3, max_probes=60, verify_bracket=0,
+                     min_steps=20000)
+
+
+def _centre(mon, nx):
+    """Periodic centre of oil mass (x) from the first circular moments."""
+    return math.atan2(mon["oil_sin"], mon["oil_cos"]) / (2.0 * math.pi) * nx
+
+
+def _wrap(d, nx):
+    while d > 0.5 * nx:
+        d -= nx
+    while d <= -0.5 * nx:
+        d += nx
+    return d
+
+
+def solve(engine, problems, **rules):
+    """problems: list of dicts with nx, lam, h0, a, tau_w, g_lo, g_hi, max_steps,
+    sigma, rho_bar.  engine: begin_probe(k, g), advance(active, steps),
+    monitors() -> list of dicts (mass, oil_flux, oil_cos, oil_sin, bad_nodes).
+    Returns a list of result dicts and, per problem, the probed g values."""
+    R = dict(DEFAULT_RULES)
+    R.update(rules)
+    n = len(problems)
+    mon = engine.monitors()
+    x_start = [_centre(mon[k], problems[k]["nx"]) for k in range(n)]
+    st = []
+    for k, p in enumerate(problems):
+        s = dict(lo=p["g_lo"], hi=p["g_hi"], widen=0, probes=0, flags=0, history=[],
+                 phase="verify_lo" if R["verify_bracket"] else "bisect")
+        s["g"] = s["lo"] if R["verify_bracket"] else math.sqrt(s["lo"] * s["hi"])
+        st.append(s)
+
+    def begin(k):
+        s = st[k]
+        s.update(t=0, X=0.0, prev=x_start[k], still=0)
+        s["history"].append(s["g"])
+        engine.begin_probe(k, s["g"])
+
+    for k in range(n):
+        begin(k)
+    active = [True] * n
+    while any(active):
+        engine.advance(list(active), R["chunk_steps"])
+        mon = engine.monitors()
+        for k in range(n):
+            if not active[k]:
+                continue
+            p, s, m = problems[k], st[k], mon[k]
+            s["t"] += R["chunk_steps"]
+            verdict = None
+            if m["bad_nodes"] > 0 or not np.isfinite(m["oil_cos"] + m["oil_sin"] + m["oil_flux"]):
+                s["flags"] |= UNSTABLE
+                verdict = "moving"
+            else:
+                x = _centre(m, p["nx"])
+                s["X"] += _wrap(x - s["prev"], p["nx"])
+                s["prev"] = x
+                if s["X"] >= R["move_frac"] * p["lam"]:
+                    verdict = "moving"
+                else:
+                    nu_w = (p["tau_w"] - 0.5) / 3.0
+                    u_ref = s["g"] * p["h0"] ** 2 / (3.0 * nu_w)
+                    U = m["oil_flux"] / m["mass"][0] if m["mass"][0] > 0 else 0.0
+                    if s["t"] >= R["min_steps"] and abs(U) < R["still_frac"] * u_ref:
+                        s["still"] += 1
+                    else:
+                        s["still"] = 0
+                    if s["still"] >= R["still_chunks"] and s["X"] < R["creep_frac"] * p["lam"]:
+                        verdict = "static"
+                    elif s["t"] >= p["max_steps"]:
+                        s["flags"] |= UNDECIDED
+                        verdict = ("moving" if s["X"] >= R["creep_frac"] * p["lam"]
+                                   else "static")
+            if verdict is None:
+                continue
+            s["probes"] += 1
+            moving = verdict == "moving"
+            if s["phase"] == "verify_lo":
+                if moving and s["widen"] < 8:
+                    s["widen"] += 1
+                    s["flags"] |= WIDENED
+                    s["hi"] = s["lo"]
+                    s["lo"] /= math.sqrt(10.0)
+                    s["g"] = s["lo"]
+                else:
+                    s["phase"] = "verify_hi"
+                    s["g"] = s["hi"]
+            elif s["phase"] == "verify_hi":
+                if not moving and s["widen"] < 8:
+                    s["widen"] += 1
+                    s["flags"] |= WIDENED
+                    s["lo"] = s["hi"]
+                    s["hi"] *= math.sqrt(10.0)
+                    s["g"] = s["hi"]
+                else:
+                    s["phase"] = "bisect"
+                    s["g"] = math.sqrt(s["lo"] * s["hi"])
+            else:
+                if moving:
+                    s["hi"] = s["g"]
+                else:
+                    s["lo"] = s["g"]
+                s["g"] = math.sqrt(s["lo"] * s["hi"])
+                if (s["hi"] - s["lo"]) / s["lo"] <= R["rel_tol"]:
+                    s["phase"] = "done"
+            if s["phase"] != "done" and s["probes"] >= R["max_probes"]:
+                s["flags"] |= NOT_CONVERGED
+                s["phase"] = "done"
+            if s["phase"] == "done":
+                active[k] = False
+            else:
+                begin(k)
+    out = []
+    for k, p in enumerate(problems):
+        s = st[k]
+        g = math.sqrt(s["lo"] * s["hi"])
+        out.append(dict(g_lo=s["lo"], g_hi=s["hi"], g_crit=g, probes=s["probes"],
+                        flags=s["flags"], history=s["history"],
+                        bo_crit=p["rho_bar"] * g * p["nx"] * (p["h0"] - p["a"]) / p["sigma"]))
+    return out
+
+
+class OracleEngine:
+    """Oracle lattices as a critical-pressure engine: equilibrate without
+    forcing, keep that state, and restart every probe from it."""
+
+    def __init__(self, lattices, equil_steps):
+        self.lat = lattices
+        for L in self.lat:
+            L.set_body_force(0.0)
+            L.step(equil_steps)
+        self.snap = [L.copy_state() for L in self.lat]
+
+    def begin_probe(self, k, g):
+        self.lat[k].restore_state(self.snap[k])
+        self.lat[k].set_body_force(g)
+
+    def advance(self, active, steps):
+        for k, L in enumerate(self.lat):
+            if active[k]:
+                try:
+                    L.step(steps)
+                except FloatingPointError:
+                    pass  # reported through bad_nodes by the next monitors() call
+
+    def monitors(self):
+        out = []
+        for L in self.lat:
+            m = L.moments()["mon"]
+            out.append({"mass": (m[0], m[1]), "momentum": (m[2], m[3]), "oil_flux": m[4],
+                        "oil_cos": m[5], "oil_sin": m[6], "bad_nodes": m[7]})
+        return out

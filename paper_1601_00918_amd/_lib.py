@@ -21,8 +21,13 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 EXPORTED = [
     "lbm_last_error", "lbm_version", "lbm_required_bytes", "lbm_init", "lbm_step",
     "lbm_time", "lbm_set_fluid", "lbm_moments", "lbm_monitors", "lbm_get_populations",
-    "lbm_fluid_mask", "lbm_set_tiling", "lbm_get_tiling", "lbm_destroy",
+    "lbm_fluid_mask", "lbm_set_tiling", "lbm_get_tiling", "lbm_destroy", "lbm_set_active",
+    "lbm_snapshot_save", "lbm_snapshot_restore", "lbm_cp_default_options",
+    "lbm_cp_required_bytes", "lbm_critical_pressure", "lbm_cp_drive",
 ]
+
+OPT_SNAPSHOT = 0x100
+CP_UNDECIDED, CP_UNSTABLE, CP_WIDENED, CP_NOT_CONVERGED = 1, 2, 4, 8
 
 
 class LbmGeom(ctypes.Structure):
@@ -49,6 +54,39 @@ class LbmMonitor(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double * 2), ("momentum", ctypes.c_double * 2),
                 ("oil_flux", ctypes.c_double), ("oil_cos", ctypes.c_double),
                 ("oil_sin", ctypes.c_double), ("bad_nodes", ctypes.c_double)]
+
+
+class LbmCpProblem(ctypes.Structure):
+    _fields_ = [("geom", LbmGeom), ("fluid", LbmFluid), ("init", LbmInitFields),
+                ("sigma", ctypes.c_double), ("rho_bar", ctypes.c_double),
+                ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
+                ("equil_steps", ctypes.c_int64), ("max_steps", ctypes.c_int64)]
+
+
+class LbmCpOptions(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("move_frac", ctypes.c_double),
+                ("creep_frac", ctypes.c_double), ("still_frac", ctypes.c_double),
+                ("chunk_steps", ctypes.c_int32), ("still_chunks", ctypes.c_int32),
+                ("max_probes", ctypes.c_int32), ("verify_bracket", ctypes.c_int32),
+                ("min_steps", ctypes.c_int64)]
+
+
+class LbmCpResult(ctypes.Structure):
+    _fields_ = [("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
+                ("g_crit", ctypes.c_double), ("bo_crit", ctypes.c_double),
+                ("probes", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("steps", ctypes.c_int64)]
+
+
+CP_BEGIN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double)
+CP_ADVANCE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
+                              ctypes.c_int64)
+CP_MONITORS = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(LbmMonitor))
+
+
+class LbmCpEngine(ctypes.Structure):
+    _fields_ = [("begin_probe", CP_BEGIN), ("advance", CP_ADVANCE), ("monitors", CP_MONITORS),
+                ("user", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -85,10 +123,22 @@ def load():
     lib.lbm_set_tiling.argtypes = [vp, i32, i32]
     lib.lbm_get_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
+    lib.lbm_set_active.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    lib.lbm_snapshot_save.argtypes = [vp]
+    lib.lbm_snapshot_restore.argtypes = [vp, i32]
+    lib.lbm_cp_default_options.argtypes = [ctypes.POINTER(LbmCpOptions)]
+    lib.lbm_cp_default_options.restype = None
+    lib.lbm_cp_required_bytes.argtypes = [ctypes.POINTER(LbmCpProblem), i32, ctypes.POINTER(sz)]
+    lib.lbm_critical_pressure.argtypes = [ctypes.POINTER(LbmCpProblem), i32,
+                                          ctypes.POINTER(LbmCpOptions), vp, sz, vp,
+                                          ctypes.POINTER(LbmCpResult)]
+    lib.lbm_cp_drive.argtypes = [ctypes.POINTER(LbmCpEngine), ctypes.POINTER(LbmCpProblem), i32,
+                                 ctypes.POINTER(LbmCpOptions), ctypes.POINTER(LbmCpResult)]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy"):
+        if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy",
+                        "lbm_cp_default_options"):
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib

@@ -9,9 +9,10 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (GEOM_BOX, GEOM_CHANNEL, GEOM_MASK, INIT_DROPLET, INIT_FIELD, INIT_LAYERS,
-                   INIT_SLUG, INIT_UNIFORM, STORE_BF16, STORE_F16, STORE_F32, LbmFluid, LbmGeom,
-                   LbmInitFields, LbmMonitor, check)
+from ._lib import (CP_ADVANCE, CP_BEGIN, CP_MONITORS, GEOM_BOX, GEOM_CHANNEL, GEOM_MASK,
+                   INIT_DROPLET, INIT_FIELD, INIT_LAYERS, INIT_SLUG, INIT_UNIFORM, OPT_SNAPSHOT,
+                   STORE_BF16, STORE_F16, STORE_F32, LbmCpEngine, LbmCpOptions, LbmCpProblem,
+                   LbmCpResult, LbmFluid, LbmGeom, LbmInitFields, LbmMonitor, check)
 
 _GEOM_KINDS = {"box": GEOM_BOX, "channel": GEOM_CHANNEL, "mask": GEOM_MASK}
 _INIT_KINDS = {"uniform": INIT_UNIFORM, "droplet": INIT_DROPLET, "layers": INIT_LAYERS,
@@ -86,18 +87,24 @@ def _arr(structs, typ):
     return a
 
 
-def lbm_required_bytes(geoms, storage="f32"):
+def _storage_code(storage, snapshot=False):
+    return _STORAGE[storage] | (OPT_SNAPSHOT if snapshot else 0)
+
+
+def lbm_required_bytes(geoms, storage="f32", snapshot=False):
     n = ctypes.c_size_t()
     ga = _arr(geoms, LbmGeom)
-    check(_lib.load().lbm_required_bytes(ga, len(geoms), _STORAGE[storage], ctypes.byref(n)),
-          "lbm_required_bytes")
+    check(_lib.load().lbm_required_bytes(ga, len(geoms), _storage_code(storage, snapshot),
+                                         ctypes.byref(n)), "lbm_required_bytes")
     return n.value
 
 
-def lbm_init(geoms, fluids, inits, storage, workspace_ptr, workspace_bytes, stream_ptr):
+def lbm_init(geoms, fluids, inits, storage, workspace_ptr, workspace_bytes, stream_ptr,
+             snapshot=False):
     ctx = ctypes.c_void_p()
     check(_lib.load().lbm_init(_arr(geoms, LbmGeom), _arr(fluids, LbmFluid),
-                               _arr(inits, LbmInitFields), len(geoms), _STORAGE[storage],
+                               _arr(inits, LbmInitFields), len(geoms),
+                               _storage_code(storage, snapshot),
                                ctypes.c_void_p(workspace_ptr), workspace_bytes,
                                ctypes.c_void_p(stream_ptr), ctypes.byref(ctx)), "lbm_init")
     return ctx
@@ -166,8 +173,111 @@ def lbm_get_tiling(ctx):
     return bx.value, st.value, n.value
 
 
+def lbm_set_active(ctx, active):
+    a = (ctypes.c_uint8 * len(active))(*[1 if v else 0 for v in active])
+    check(_lib.load().lbm_set_active(ctx, a), "lbm_set_active")
+
+
+def lbm_snapshot_save(ctx):
+    check(_lib.load().lbm_snapshot_save(ctx), "lbm_snapshot_save")
+
+
+def lbm_snapshot_restore(ctx, inst=-1):
+    check(_lib.load().lbm_snapshot_restore(ctx, int(inst)), "lbm_snapshot_restore")
+
+
 def lbm_destroy(ctx):
     _lib.load().lbm_destroy(ctx)
+
+
+# ---------------------------------------------------------- critical pressure --
+def cp_options(**overrides):
+    """Default critical-pressure options (include/lbm.h) with overrides."""
+    o = LbmCpOptions()
+    _lib.load().lbm_cp_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def cp_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, keep=None):
+    """Critical-pressure problem from a channel workload dict."""
+    g, f, i = structs_from_config(cfg, None, keep)
+    p = LbmCpProblem()
+    p.geom, p.fluid, p.init = g, f, i
+    p.sigma, p.rho_bar = float(sigma), float(rho_bar)
+    p.g_lo, p.g_hi = float(g_lo), float(g_hi)
+    p.equil_steps, p.max_steps = int(equil_steps), int(max_steps)
+    return p
+
+
+def _result_dict(r):
+    return {"g_lo": r.g_lo, "g_hi": r.g_hi, "g_crit": r.g_crit, "bo_crit": r.bo_crit,
+            "probes": r.probes, "flags": r.flags, "steps": r.steps}
+
+
+def lbm_cp_required_bytes(problems):
+    n = ctypes.c_size_t()
+    check(_lib.load().lbm_cp_required_bytes(_arr(problems, LbmCpProblem), len(problems),
+                                            ctypes.byref(n)), "lbm_cp_required_bytes")
+    return n.value
+
+
+def lbm_critical_pressure(problems, opts=None, device="cuda", stream=None):
+    """Solve the problems together on the GPU; returns a list of result dicts."""
+    import torch  # device memory and streams only
+
+    _lib.load()
+    nbytes = lbm_cp_required_bytes(problems)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    st = stream if stream is not None else torch.cuda.Stream(ws.device)
+    res = (LbmCpResult * len(problems))()
+    o = opts if opts is not None else cp_options()
+    check(_lib.load().lbm_critical_pressure(_arr(problems, LbmCpProblem), len(problems),
+                                            ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
+                                            nbytes, ctypes.c_void_p(st.cuda_stream), res),
+          "lbm_critical_pressure")
+    del ws
+    return [_result_dict(r) for r in res]
+
+
+def lbm_cp_drive(engine, problems, opts=None):
+    """Run the library's bisection driver on a Python engine object with methods
+    begin_probe(k, g), advance(active_list, steps), monitors() -> list of
+    monitor dicts (keys as returned by lbm_monitors)."""
+    n = len(problems)
+
+    def _begin(user, k, g):
+        try:
+            engine.begin_probe(int(k), float(g))
+            return 0
+        except Exception:  # reported as an engine failure by the driver
+            return 1
+
+    def _advance(user, active, steps):
+        try:
+            engine.advance([active[k] for k in range(n)], int(steps))
+            return 0
+        except Exception:
+            return 1
+
+    def _monitors(user, out):
+        try:
+            for k, m in enumerate(engine.monitors()):
+                out[k].mass[0], out[k].mass[1] = m["mass"]
+                out[k].momentum[0], out[k].momentum[1] = m["momentum"]
+                out[k].oil_flux, out[k].oil_cos = m["oil_flux"], m["oil_cos"]
+                out[k].oil_sin, out[k].bad_nodes = m["oil_sin"], m["bad_nodes"]
+            return 0
+        except Exception:
+            return 1
+
+    cb = LbmCpEngine(CP_BEGIN(_begin), CP_ADVANCE(_advance), CP_MONITORS(_monitors), None)
+    res = (LbmCpResult * n)()
+    o = opts if opts is not None else cp_options()
+    check(_lib.load().lbm_cp_drive(ctypes.byref(cb), _arr(problems, LbmCpProblem), n,
+                                   ctypes.byref(o), res), "lbm_cp_drive")
+    return [_result_dict(r) for r in res]
 
 
 # ------------------------------------------------------------- convenience ---
@@ -178,7 +288,8 @@ class Simulation:
     rho_s, g, init); fields: optional list (same length) of explicit initial
     density arrays [2, ny, nx] (None entries use the config's preset)."""
 
-    def __init__(self, configs, fields=None, storage="f32", device="cuda"):
+    def __init__(self, configs, fields=None, storage="f32", device="cuda", snapshot=False,
+                 stream=None):
         import torch  # device memory and streams only
 
         _lib.load()
@@ -192,19 +303,20 @@ class Simulation:
             fluids.append(f)
             inits.append(i)
         self.fluids = fluids
-        nbytes = lbm_required_bytes(geoms, storage)
+        nbytes = lbm_required_bytes(geoms, storage, snapshot)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = torch.cuda.current_stream(self.workspace.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(
+            self.workspace.device)
         self.ctx = lbm_init(geoms, fluids, inits, storage, self.workspace.data_ptr(), nbytes,
-                            self.stream.cuda_stream)
+                            self.stream.cuda_stream, snapshot)
         self.workspace_bytes = nbytes
         del keep
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            lbm_destroy(ctx)
-            self.ctx = None
+        if ctx and _lib is not None and _lib._LIB is not None:
+            _lib._LIB.lbm_destroy(ctx)
+        self.ctx = None
 
     @property
     def n_inst(self):
@@ -232,6 +344,15 @@ class Simulation:
     def populations(self, inst=0):
         c = self.configs[inst]
         return lbm_get_populations(self.ctx, inst, c["nx"], c["ny"])
+
+    def set_active(self, active):
+        lbm_set_active(self.ctx, active)
+
+    def snapshot_save(self):
+        lbm_snapshot_save(self.ctx)
+
+    def snapshot_restore(self, inst=-1):
+        lbm_snapshot_restore(self.ctx, inst)
 
     def set_tiling(self, bx, strip_rows):
         lbm_set_tiling(self.ctx, bx, strip_rows)

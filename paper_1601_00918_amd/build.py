@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_driver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -22,7 +22,10 @@ def build(verbose: bool = False) -> str:
     """Compile every source for gfx950 and link liblbm.so; returns its path."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-x", "hip", srcs[0], "-x", "hip", srcs[1], "-o", tmp]
+    cmd = [HIPCC, *FLAGS]
+    for src in srcs:
+        cmd += ["-x", "hip", src]
+    cmd += ["-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

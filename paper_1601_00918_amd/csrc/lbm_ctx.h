@@ -1,0 +1,87 @@
+// Host-side context of the C ABI, shared by the runtime (lbm_runtime.cpp) and
+// the critical-pressure driver (lbm_driver.cpp).  Not part of the public ABI.
+#pragma once
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+namespace lbm {
+
+// Host description of one instance.
+struct InstHost {
+    int kind;
+    int nx, ny;
+    int pitch;
+    int64_t elems;  // population elements of this instance (18 * pitch * ny, padded)
+    int64_t f_off;
+    std::vector<Col> cols;  // per column fluid run
+};
+
+// Workspace carving (byte offsets into the caller's device workspace).
+struct Layout {
+    size_t buf_bytes;  // one population buffer
+    size_t off_buf[2], off_snap, off_inst, off_items, off_cols, off_partial, off_mon,
+        off_first, off_count, off_stage, total;
+    int64_t n_items_max;
+    int64_t max_nodes;
+};
+
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    using InstHost = lbm::InstHost;
+    using InstDev = lbm::InstDev;
+    using Item = lbm::Item;
+    using Layout = lbm::Layout;
+    using Col = lbm::Col;
+    int n_inst = 0;
+    int storage = LBM_STORE_F32;
+    std::vector<InstHost> ih;
+    std::vector<InstDev> idv;
+    std::vector<Item> items;
+    std::vector<int32_t> item_first, item_count;
+    Layout L{};
+    char* ws = nullptr;
+    float* buf[2] = {nullptr, nullptr};
+    InstDev* inst_d = nullptr;
+    Item* items_d = nullptr;
+    Col* cols_d = nullptr;
+    double* partial_d = nullptr;
+    double* mon_d = nullptr;
+    int32_t* first_d = nullptr;
+    int32_t* count_d = nullptr;
+    double* stage_d = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    int64_t t = 0;
+    int bx = 256;
+    int strip = 8;
+    // Work items being stepped: a copy of the items of the active instances,
+    // stored on the device after the full list (at items_d + L.n_items_max).
+    std::vector<uint8_t> active;
+    int n_active_items = 0;
+    // Buffer (0/1) holding each instance's current state: active instances
+    // follow `cur`; an inactive one stays where it was when it stopped.
+    std::vector<int> ipar;
+    // Snapshot buffer (optional, LBM_OPT_SNAPSHOT).
+    float* snap = nullptr;
+    int64_t snap_t = -1;
+    // Cached graph of kGraphSteps step launches (non-null streams only).
+    hipGraphExec_t graph = nullptr;
+    int graph_cur = -1;
+    bool graph_dirty = true;
+    ~lbm_ctx();
+};
+
+namespace lbm {
+// Error reporting shared by the runtime and the driver.
+lbm_status fail(lbm_status st, const char* fmt, ...);
+}  // namespace lbm
+
+

@@ -1,0 +1,390 @@
+// Critical-pressure driver (Sec. 3.4): bisection in log g over probes that
+// restart from an equilibrated state, with the motion / rest classification
+// documented in include/lbm.h.  The same state machine runs on the HIP engine
+// (lbm_critical_pressure: every problem in one batched launch per step,
+// finished probes restarted at once, finished problems dropped from the
+// launch) and on caller callbacks (lbm_cp_drive).
+#include "lbm_ctx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace lbm;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int kMaxWiden = 8;
+
+struct CpEngine {
+    virtual ~CpEngine() {}
+    virtual lbm_status begin_probe(int k, double g) = 0;
+    virtual lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) = 0;
+    virtual lbm_status monitors(std::vector<lbm_monitor>& mon) = 0;
+};
+
+enum Outcome { kNone, kStatic, kMoving };
+enum Phase { kVerifyLo, kVerifyHi, kBisect, kDone };
+
+struct ProbeState {
+    Phase phase = kBisect;
+    double g_lo = 0, g_hi = 0, g = 0;
+    int widen = 0;
+    // current probe
+    int64_t probe_steps = 0;
+    double X = 0.0, xc_prev = 0.0;
+    int still = 0;
+};
+
+double centroid(const lbm_monitor& m, double nx)
+{
+    return std::atan2(m.oil_sin, m.oil_cos) / kTwoPi * nx;
+}
+
+double wrap_half(double d, double nx)
+{
+    while (d > 0.5 * nx)
+        d -= nx;
+    while (d <= -0.5 * nx)
+        d += nx;
+    return d;
+}
+
+lbm_status check_problem(const lbm_cp_problem& p, int k)
+{
+    if (p.geom.kind != LBM_GEOM_CHANNEL)
+        return fail(LBM_ERR_INVALID, "problem %d: critical pressure needs a channel geometry", k);
+    if (!(p.g_lo > 0.0) || !(p.g_hi > p.g_lo) || !std::isfinite(p.g_hi))
+        return fail(LBM_ERR_INVALID, "problem %d: bracket must satisfy 0 < g_lo < g_hi", k);
+    if (!(p.sigma > 0.0) || !(p.rho_bar > 0.0))
+        return fail(LBM_ERR_INVALID, "problem %d: sigma and rho_bar must be > 0", k);
+    if (p.max_steps <= 0 || p.equil_steps < 0)
+        return fail(LBM_ERR_INVALID, "problem %d: bad step counts", k);
+    if (!(p.fluid.tau[1] > 0.5))
+        return fail(LBM_ERR_INVALID, "problem %d: tau_w must be > 1/2", k);
+    return LBM_OK;
+}
+
+lbm_status check_options(const lbm_cp_options& o)
+{
+    if (!(o.rel_tol > 0.0) || !(o.move_frac > 0.0) || !(o.creep_frac > 0.0) ||
+        !(o.still_frac > 0.0) || o.chunk_steps < 2 || (o.chunk_steps & 1) || o.still_chunks < 1 ||
+        o.max_probes < 1 || o.min_steps < 0)
+        return fail(LBM_ERR_INVALID, "invalid critical-pressure options");
+    return LBM_OK;
+}
+
+// Classify the running probe of problem k from its monitors.
+Outcome classify(const lbm_cp_problem& p, const lbm_cp_options& o, ProbeState& s,
+                 const lbm_monitor& m, int32_t& flags)
+{
+    const double nx = p.geom.nx;
+    const double lam = p.geom.lambda;
+    if (m.bad_nodes > 0.0 || !std::isfinite(m.oil_cos + m.oil_sin + m.oil_flux)) {
+        flags |= LBM_CP_UNSTABLE;
+        return kMoving;
+    }
+    const double xc = centroid(m, nx);
+    s.X += wrap_half(xc - s.xc_prev, nx);
+    s.xc_prev = xc;
+    if (s.X >= o.move_frac * lam)
+        return kMoving;
+    const double nu_w = (p.fluid.tau[1] - 0.5) / 3.0;
+    const double u_ref = s.g * p.geom.h0 * p.geom.h0 / (3.0 * nu_w);
+    const double U = m.mass[0] > 0.0 ? m.oil_flux / m.mass[0] : 0.0;
+    if (s.probe_steps >= o.min_steps && std::fabs(U) < o.still_frac * u_ref)
+        ++s.still;
+    else
+        s.still = 0;
+    if (s.still >= o.still_chunks && s.X < o.creep_frac * lam)
+        return kStatic;
+    if (s.probe_steps >= p.max_steps) {
+        flags |= LBM_CP_UNDECIDED;
+        return s.X >= o.creep_frac * lam ? kMoving : kStatic;
+    }
+    return kNone;
+}
+
+lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_cp_options& o,
+                  lbm_cp_result* res, const std::vector<int64_t>& steps0)
+{
+    std::vector<ProbeState> st(n);
+    std::vector<lbm_monitor> mon(n);
+    lbm_status e = eng.monitors(mon);
+    if (e != LBM_OK)
+        return e;
+    std::vector<double> xc0(n);
+    for (int k = 0; k < n; ++k) {
+        const lbm_cp_problem& p = probs[k];
+        xc0[k] = centroid(mon[k], p.geom.nx);
+        ProbeState& s = st[k];
+        s.g_lo = p.g_lo;
+        s.g_hi = p.g_hi;
+        s.phase = o.verify_bracket ? kVerifyLo : kBisect;
+        s.g = o.verify_bracket ? s.g_lo : std::sqrt(s.g_lo * s.g_hi);
+        std::memset(&res[k], 0, sizeof(lbm_cp_result));
+        res[k].steps = steps0[k];
+    }
+    auto start = [&](int k) -> lbm_status {
+        ProbeState& s = st[k];
+        s.probe_steps = 0;
+        s.X = 0.0;
+        s.xc_prev = xc0[k];
+        s.still = 0;
+        return eng.begin_probe(k, s.g);
+    };
+    for (int k = 0; k < n; ++k)
+        if ((e = start(k)) != LBM_OK)
+            return e;
+
+    std::vector<uint8_t> active(n, 1);
+    int remaining = n;
+    while (remaining > 0) {
+        if ((e = eng.advance(active, o.chunk_steps)) != LBM_OK)
+            return e;
+        if ((e = eng.monitors(mon)) != LBM_OK)
+            return e;
+        for (int k = 0; k < n; ++k) {
+            if (!active[k])
+                continue;
+            const lbm_cp_problem& p = probs[k];
+            ProbeState& s = st[k];
+            lbm_cp_result& r = res[k];
+            s.probe_steps += o.chunk_steps;
+            r.steps += o.chunk_steps;
+            const Outcome out = classify(p, o, s, mon[k], r.flags);
+            if (out == kNone)
+                continue;
+            ++r.probes;
+            const bool moving = out == kMoving;
+            switch (s.phase) {
+            case kVerifyLo:
+                if (moving && s.widen < kMaxWiden) {
+                    ++s.widen;
+                    r.flags |= LBM_CP_WIDENED;
+                    s.g_hi = s.g_lo;
+                    s.g_lo /= std::sqrt(10.0);
+                    s.g = s.g_lo;
+                } else {
+                    s.phase = kVerifyHi;
+                    s.g = s.g_hi;
+                }
+                break;
+            case kVerifyHi:
+                if (!moving && s.widen < kMaxWiden) {
+                    ++s.widen;
+                    r.flags |= LBM_CP_WIDENED;
+                    s.g_lo = s.g_hi;
+                    s.g_hi *= std::sqrt(10.0);
+                    s.g = s.g_hi;
+                } else {
+                    s.phase = kBisect;
+                    s.g = std::sqrt(s.g_lo * s.g_hi);
+                }
+                break;
+            default:
+                if (moving)
+                    s.g_hi = s.g;
+                else
+                    s.g_lo = s.g;
+                s.g = std::sqrt(s.g_lo * s.g_hi);
+                if ((s.g_hi - s.g_lo) / s.g_lo <= o.rel_tol)
+                    s.phase = kDone;
+                break;
+            }
+            if (s.phase != kDone && r.probes >= o.max_probes) {
+                r.flags |= LBM_CP_NOT_CONVERGED;
+                s.phase = kDone;
+            }
+            if (s.phase == kDone) {
+                active[k] = 0;
+                --remaining;
+            } else if ((e = start(k)) != LBM_OK) {
+                return e;
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        const lbm_cp_problem& p = probs[k];
+        lbm_cp_result& r = res[k];
+        r.g_lo = st[k].g_lo;
+        r.g_hi = st[k].g_hi;
+        r.g_crit = std::sqrt(r.g_lo * r.g_hi);
+        const double D = p.geom.h0 - p.geom.a;
+        r.bo_crit = p.rho_bar * r.g_crit * (double)p.geom.nx * D / p.sigma;
+    }
+    return LBM_OK;
+}
+
+// ---- engine over the library's own context -----------------------------------
+struct HipEngine : CpEngine {
+    lbm_ctx* ctx = nullptr;
+    std::vector<lbm_fluid> fluids;
+    std::vector<uint8_t> cur_active;
+
+    lbm_status begin_probe(int k, double g) override
+    {
+        lbm_status e = lbm_snapshot_restore(ctx, k);
+        if (e != LBM_OK)
+            return e;
+        fluids[k].g[0] = g;
+        fluids[k].g[1] = 0.0;
+        return lbm_set_fluid(ctx, k, &fluids[k]);
+    }
+    lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) override
+    {
+        if (active != cur_active) {
+            lbm_status e = lbm_set_active(ctx, active.data());
+            if (e != LBM_OK)
+                return e;
+            cur_active = active;
+        }
+        return lbm_step(ctx, steps);
+    }
+    lbm_status monitors(std::vector<lbm_monitor>& mon) override
+    {
+        return lbm_monitors(ctx, mon.data());
+    }
+};
+
+// ---- engine over caller callbacks --------------------------------------------
+struct CallbackEngine : CpEngine {
+    const lbm_cp_engine* cb = nullptr;
+    lbm_status begin_probe(int k, double g) override
+    {
+        return cb->begin_probe(cb->user, k, g) == 0
+                   ? LBM_OK
+                   : fail(LBM_ERR_INVALID, "engine begin_probe(%d) failed", k);
+    }
+    lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) override
+    {
+        return cb->advance(cb->user, active.data(), steps) == 0
+                   ? LBM_OK
+                   : fail(LBM_ERR_INVALID, "engine advance failed");
+    }
+    lbm_status monitors(std::vector<lbm_monitor>& mon) override
+    {
+        return cb->monitors(cb->user, mon.data()) == 0
+                   ? LBM_OK
+                   : fail(LBM_ERR_INVALID, "engine monitors failed");
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void lbm_cp_default_options(lbm_cp_options* o)
+{
+    if (!o)
+        return;
+    std::memset(o, 0, sizeof *o);
+    o->rel_tol = 0.005;
+    o->move_frac = 0.5;
+    o->creep_frac = 0.25;
+    o->still_frac = 1e-3;
+    o->chunk_steps = 1000;
+    o->still_chunks = 3;
+    o->max_probes = 60;
+    o->verify_bracket = 0;
+    o->min_steps = 20000;
+}
+
+lbm_status lbm_cp_required_bytes(const lbm_cp_problem* probs, int32_t n, size_t* bytes)
+{
+    if (!probs || n < 1 || !bytes)
+        return fail(LBM_ERR_INVALID, "lbm_cp_required_bytes: bad argument");
+    std::vector<lbm_geom> geoms(n);
+    for (int k = 0; k < n; ++k)
+        geoms[k] = probs[k].geom;
+    return lbm_required_bytes(geoms.data(), n, LBM_STORE_F32 | LBM_OPT_SNAPSHOT, bytes);
+}
+
+lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
+                                 const lbm_cp_options* opts, void* device_workspace,
+                                 size_t workspace_bytes, void* hip_stream,
+                                 lbm_cp_result* results)
+{
+    if (!probs || n < 1 || !results)
+        return fail(LBM_ERR_INVALID, "lbm_critical_pressure: bad argument");
+    lbm_cp_options o;
+    if (opts)
+        o = *opts;
+    else
+        lbm_cp_default_options(&o);
+    lbm_status e = check_options(o);
+    if (e != LBM_OK)
+        return e;
+    std::vector<lbm_geom> geoms(n);
+    std::vector<lbm_fluid> fluids(n);
+    std::vector<lbm_init_fields> inits(n);
+    for (int k = 0; k < n; ++k) {
+        if ((e = check_problem(probs[k], k)) != LBM_OK)
+            return e;
+        geoms[k] = probs[k].geom;
+        fluids[k] = probs[k].fluid;
+        fluids[k].g[0] = fluids[k].g[1] = 0.0;
+        inits[k] = probs[k].init;
+    }
+    HipEngine eng;
+    e = lbm_init(geoms.data(), fluids.data(), inits.data(), n, LBM_STORE_F32 | LBM_OPT_SNAPSHOT,
+                 device_workspace, workspace_bytes, hip_stream, &eng.ctx);
+    if (e != LBM_OK)
+        return e;
+    eng.fluids = fluids;
+    eng.cur_active.assign(n, 1);
+    // Unforced equilibration, each problem for its own number of steps.
+    std::vector<int64_t> steps0(n, 0);
+    int64_t done = 0;
+    for (;;) {
+        std::vector<uint8_t> act(n, 0);
+        int64_t next = -1;
+        for (int k = 0; k < n; ++k)
+            if (probs[k].equil_steps > done) {
+                act[k] = 1;
+                next = next < 0 ? probs[k].equil_steps : std::min(next, probs[k].equil_steps);
+            }
+        if (next < 0)
+            break;
+        if ((e = eng.advance(act, next - done)) != LBM_OK)
+            break;
+        for (int k = 0; k < n; ++k)
+            if (act[k])
+                steps0[k] += next - done;
+        done = next;
+    }
+    if (e == LBM_OK)
+        e = lbm_snapshot_save(eng.ctx);
+    if (e == LBM_OK)
+        e = cp_run(eng, probs, n, o, results, steps0);
+    lbm_destroy(eng.ctx);
+    return e;
+}
+
+lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs, int32_t n,
+                        const lbm_cp_options* opts, lbm_cp_result* results)
+{
+    if (!engine || !engine->begin_probe || !engine->advance || !engine->monitors || !probs ||
+        n < 1 || !results)
+        return fail(LBM_ERR_INVALID, "lbm_cp_drive: bad argument");
+    lbm_cp_options o;
+    if (opts)
+        o = *opts;
+    else
+        lbm_cp_default_options(&o);
+    lbm_status e = check_options(o);
+    if (e != LBM_OK)
+        return e;
+    for (int k = 0; k < n; ++k)
+        if ((e = check_problem(probs[k], k)) != LBM_OK)
+            return e;
+    CallbackEngine eng;
+    eng.cb = engine;
+    return cp_run(eng, probs, n, o, results, std::vector<int64_t>(n, 0));
+}
+
+}  // extern "C"

@@ -1,8 +1,7 @@
 // Host runtime behind the C ABI of include/lbm.h: parameter validation,
 // voxelisation into column runs, work-item tiling, workspace carving, launch
 // sequencing and device-to-host export.
-#include "lbm.h"
-#include "lbm_internal.h"
+#include "lbm_ctx.h"
 
 #include <hip/hip_runtime.h>
 
@@ -21,7 +20,9 @@ namespace {
 
 thread_local std::string g_last_error;
 
-lbm_status fail(lbm_status st, const char* fmt, ...)
+}  // namespace
+
+lbm_status lbm::fail(lbm_status st, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -31,6 +32,8 @@ lbm_status fail(lbm_status st, const char* fmt, ...)
     g_last_error = buf;
     return st;
 }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -42,18 +45,9 @@ lbm_status fail(lbm_status st, const char* fmt, ...)
 constexpr size_t kAlign = 256;
 constexpr int kMinBx = 64;
 constexpr int kMinStrip = 4;
+constexpr int kGraphSteps = 64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Host description of one instance.
-struct InstHost {
-    int kind;
-    int nx, ny;
-    int pitch;
-    int64_t elems;  // population elements of this instance (18 * pitch * ny, padded)
-    int64_t f_off;
-    std::vector<Col> cols;  // per column fluid run
-};
 
 // Fluid runs per column for a geometry; returns false with a message on error.
 bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
@@ -162,16 +156,10 @@ int64_t max_items(const lbm_geom& g)
     return (int64_t)((g.nx + kMinBx - 1) / kMinBx) * ((g.ny + kMinStrip - 1) / kMinStrip);
 }
 
-struct Layout {
-    size_t buf_bytes;  // one population buffer
-    size_t off_buf[2], off_inst, off_items, off_cols, off_partial, off_mon, off_first,
-        off_count, off_stage, total;
-    int64_t n_items_max;
-    int64_t max_nodes;
-};
-
-Layout layout_of(const lbm_geom* geoms, int n_inst, int storage)
+Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
 {
+    const int storage = storage_and_opts & 0xff;
+    const bool with_snap = (storage_and_opts & LBM_OPT_SNAPSHOT) != 0;
     Layout L{};
     int64_t elems = 0, ncols = 0;
     L.n_items_max = 0;
@@ -189,14 +177,17 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage)
     o += L.buf_bytes;
     L.off_buf[1] = o;
     o += L.buf_bytes;
+    L.off_snap = o;
+    if (with_snap)
+        o += L.buf_bytes;
     L.off_inst = o;
     o = align_up(o + sizeof(InstDev) * n_inst, kAlign);
-    L.off_items = o;
-    o = align_up(o + sizeof(Item) * L.n_items_max, kAlign);
+    L.off_items = o;  // full item list, then the active-instance list
+    o = align_up(o + 2 * sizeof(Item) * L.n_items_max, kAlign);
     L.off_cols = o;
     o = align_up(o + sizeof(Col) * ncols, kAlign);
     L.off_partial = o;
-    o = align_up(o + sizeof(double) * kMonWidth * L.n_items_max, kAlign);
+    o = align_up(o + 2 * sizeof(double) * kMonWidth * L.n_items_max, kAlign);
     L.off_mon = o;
     o = align_up(o + sizeof(double) * kMonWidth * n_inst, kAlign);
     L.off_first = o;
@@ -211,30 +202,11 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage)
 
 }  // namespace
 
-struct lbm_ctx {
-    int n_inst = 0;
-    int storage = LBM_STORE_F32;
-    std::vector<InstHost> ih;
-    std::vector<InstDev> idv;
-    std::vector<Item> items;
-    std::vector<int32_t> item_first, item_count;
-    Layout L{};
-    char* ws = nullptr;
-    float* buf[2] = {nullptr, nullptr};
-    InstDev* inst_d = nullptr;
-    Item* items_d = nullptr;
-    Col* cols_d = nullptr;
-    double* partial_d = nullptr;
-    double* mon_d = nullptr;
-    int32_t* first_d = nullptr;
-    int32_t* count_d = nullptr;
-    double* stage_d = nullptr;
-    hipStream_t stream = nullptr;
-    int cur = 0;
-    int64_t t = 0;
-    int bx = 256;
-    int strip = 32;
-};
+lbm_ctx::~lbm_ctx()
+{
+    if (graph)
+        hipGraphExecDestroy(graph);
+}
 
 namespace {
 
@@ -292,15 +264,56 @@ void build_items(lbm_ctx* c)
     }
 }
 
+// Items of the active instances, in instance order.
+std::vector<Item> active_items(const lbm_ctx* c)
+{
+    std::vector<Item> v;
+    v.reserve(c->items.size());
+    for (int k = 0; k < c->n_inst; ++k)
+        if (c->active[k])
+            v.insert(v.end(), c->items.begin() + c->item_first[k],
+                     c->items.begin() + c->item_first[k] + c->item_count[k]);
+    return v;
+}
+
 lbm_status upload_tables(lbm_ctx* c)
 {
     HIP_TRY(hipMemcpyAsync(c->items_d, c->items.data(), sizeof(Item) * c->items.size(),
                            hipMemcpyHostToDevice, c->stream));
+    const std::vector<Item> act = active_items(c);
+    c->n_active_items = (int)act.size();
+    if (!act.empty())
+        HIP_TRY(hipMemcpyAsync(c->items_d + c->L.n_items_max, act.data(), sizeof(Item) * act.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    c->graph_dirty = true;
     HIP_TRY(hipMemcpyAsync(c->first_d, c->item_first.data(), sizeof(int32_t) * c->n_inst,
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->count_d, c->item_count.data(), sizeof(int32_t) * c->n_inst,
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// Bring instance k's state into buffer `cur` (it lags behind when it was
+// inactive while the buffers swapped an odd number of times).
+lbm_status sync_instance(lbm_ctx* c, int k)
+{
+    if (c->ipar[k] == c->cur)
+        return LBM_OK;
+    const InstHost& h = c->ih[k];
+    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + h.f_off, c->buf[c->ipar[k]] + h.f_off,
+                           sizeof(float) * h.elems, hipMemcpyDeviceToDevice, c->stream));
+    c->ipar[k] = c->cur;
+    return LBM_OK;
+}
+
+lbm_status sync_all(lbm_ctx* c)
+{
+    for (int k = 0; k < c->n_inst; ++k) {
+        lbm_status st = sync_instance(c, k);
+        if (st != LBM_OK)
+            return st;
+    }
     return LBM_OK;
 }
 
@@ -327,7 +340,7 @@ lbm_status lbm_required_bytes(const lbm_geom* geoms, int32_t n_inst, int32_t sto
 {
     if (!geoms || n_inst < 1 || !bytes)
         return fail(LBM_ERR_INVALID, "lbm_required_bytes: null argument or n_inst < 1");
-    if (storage != LBM_STORE_F32)
+    if ((storage & 0xff) != LBM_STORE_F32 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
         return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
     for (int k = 0; k < n_inst; ++k) {
         lbm_status st = check_geom(geoms[k]);
@@ -348,7 +361,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     *out = nullptr;
     if (!geoms || !fluids || !inits || n_inst < 1 || !device_workspace)
         return fail(LBM_ERR_INVALID, "lbm_init: null argument or n_inst < 1");
-    if (storage != LBM_STORE_F32)
+    if ((storage & 0xff) != LBM_STORE_F32 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
         return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
     if ((uintptr_t)device_workspace % kAlign)
         return fail(LBM_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
@@ -380,7 +393,11 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     if (!c)
         return fail(LBM_ERR_INVALID, "out of host memory");
     c->n_inst = n_inst;
-    c->storage = storage;
+    c->storage = storage & 0xff;
+    if (storage & LBM_OPT_SNAPSHOT)
+        c->snap = (float*)((char*)device_workspace + L.off_snap);
+    c->active.assign(n_inst, 1);
+    c->ipar.assign(n_inst, 0);
     c->L = L;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)device_workspace;
@@ -487,17 +504,125 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
+static lbm_status step_direct(lbm_ctx* c, int64_t nsteps)
 {
-    if (!c || nsteps < 0)
-        return fail(LBM_ERR_INVALID, "lbm_step: null context or negative step count");
     for (int64_t k = 0; k < nsteps; ++k) {
-        lbm_status st = run_mode(c, kStep, 0, (int)c->items.size());
+        lbm_status st = run_mode(c, kStep, (int)c->L.n_items_max, c->n_active_items);
         if (st != LBM_OK)
             return st;
         c->cur ^= 1;
         ++c->t;
     }
+    return LBM_OK;
+}
+
+// Capture kGraphSteps step launches (an even number, so the buffers end where
+// they started) into a graph for the current buffer parity and item list.
+static lbm_status ensure_graph(lbm_ctx* c)
+{
+    if (c->graph && !c->graph_dirty && c->graph_cur == c->cur)
+        return LBM_OK;
+    if (c->graph) {
+        hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int cur0 = c->cur;
+    const int64_t t0 = c->t;
+    lbm_status st = step_direct(c, kGraphSteps);
+    c->cur = cur0;
+    c->t = t0;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != LBM_OK) {
+        if (g)
+            hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph = nullptr;
+        return fail(LBM_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    c->graph_cur = c->cur;
+    c->graph_dirty = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0)
+        return fail(LBM_ERR_INVALID, "lbm_step: null context or negative step count");
+    if (c->n_active_items == 0) {
+        c->t += nsteps;
+        return LBM_OK;
+    }
+    int64_t done = 0;
+    lbm_status st = LBM_OK;
+    if (c->stream != nullptr && nsteps >= kGraphSteps) {
+        st = ensure_graph(c);
+        if (st != LBM_OK)
+            return st;
+        for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+            c->t += kGraphSteps;
+        }
+    }
+    st = step_direct(c, nsteps - done);
+    for (int k = 0; k < c->n_inst; ++k)
+        if (c->active[k])
+            c->ipar[k] = c->cur;
+    return st;
+}
+
+lbm_status lbm_set_active(lbm_ctx* c, const uint8_t* active)
+{
+    if (!c || !active)
+        return fail(LBM_ERR_INVALID, "lbm_set_active: null argument");
+    lbm_status st = sync_all(c);
+    if (st != LBM_OK)
+        return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_inst; ++k)
+        c->active[k] = active[k] ? 1 : 0;
+    return upload_tables(c);
+}
+
+lbm_status lbm_snapshot_save(lbm_ctx* c)
+{
+    if (!c)
+        return fail(LBM_ERR_INVALID, "lbm_snapshot_save: null context");
+    if (!c->snap)
+        return fail(LBM_ERR_INVALID, "lbm_snapshot_save: context created without LBM_OPT_SNAPSHOT");
+    lbm_status st = sync_all(c);
+    if (st != LBM_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(c->snap, c->buf[c->cur], c->L.buf_bytes, hipMemcpyDeviceToDevice,
+                           c->stream));
+    c->snap_t = c->t;
+    return LBM_OK;
+}
+
+lbm_status lbm_snapshot_restore(lbm_ctx* c, int32_t inst)
+{
+    if (!c || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_snapshot_restore: bad argument");
+    if (!c->snap || c->snap_t < 0)
+        return fail(LBM_ERR_INVALID, "lbm_snapshot_restore: no snapshot saved");
+    if (inst < 0) {
+        HIP_TRY(hipMemcpyAsync(c->buf[c->cur], c->snap, c->L.buf_bytes, hipMemcpyDeviceToDevice,
+                               c->stream));
+        for (int k = 0; k < c->n_inst; ++k)
+            c->ipar[k] = c->cur;
+        return LBM_OK;
+    }
+    const InstHost& h = c->ih[inst];
+    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + h.f_off, c->snap + h.f_off,
+                           sizeof(float) * h.elems, hipMemcpyDeviceToDevice, c->stream));
+    c->ipar[inst] = c->cur;
     return LBM_OK;
 }
 
@@ -521,7 +646,10 @@ lbm_status lbm_monitors(lbm_ctx* c, lbm_monitor* mon)
 {
     if (!c || !mon)
         return fail(LBM_ERR_INVALID, "lbm_monitors: null argument");
-    lbm_status st = run_mode(c, kMonOnly, 0, (int)c->items.size());
+    lbm_status st = sync_all(c);
+    if (st != LBM_OK)
+        return st;
+    st = run_mode(c, kMonOnly, 0, (int)c->items.size());
     if (st != LBM_OK)
         return st;
     hipError_t e = launch_mon_reduce(c->partial_d, c->first_d, c->count_d, c->n_inst, c->mon_d,
@@ -537,6 +665,9 @@ lbm_status lbm_monitors(lbm_ctx* c, lbm_monitor* mon)
 
 static lbm_status export_instance(lbm_ctx* c, int inst)
 {
+    lbm_status st = sync_instance(c, inst);
+    if (st != LBM_OK)
+        return st;
     const InstHost& h = c->ih[inst];
     const size_t n = (size_t)h.nx * h.ny;
     HIP_TRY(hipMemsetAsync(c->stage_d, 0, sizeof(double) * kExportFields * n, c->stream));

@@ -1,0 +1,138 @@
+"""The library's critical-pressure driver (lbm_cp_drive) against a synthetic
+engine whose critical forcing is known, and against the oracle's independent
+implementation of the same probe rules.  CPU only."""
+import math
+
+import pytest
+
+import synth
+from oracle import driver as odrv
+from paper_1601_00918_amd import binding
+
+
+class FakeEngine:
+    """Slugs that move at speed 2e-3 + c (g - g*) / g* once g exceeds g*, and
+    otherwise creep with a decaying speed that stops well short of the
+    creep threshold.  Optionally becomes non-physical above g_bad, or creeps
+    forever (never settles) for problems listed in `creepers`."""
+
+    def __init__(self, problems, g_star, g_bad=None, creepers=()):
+        self.p = problems
+        self.g_star = g_star
+        self.g_bad = g_bad or [math.inf] * len(problems)
+        self.creepers = set(creepers)
+        self.x0 = [0.37 * p["nx"] for p in problems]
+        self.state = [dict(g=0.0, t=0, X=0.0, U=0.0) for _ in problems]
+
+    def begin_probe(self, k, g):
+        self.state[k] = dict(g=g, t=0, X=0.0, U=0.0)
+
+    def advance(self, active, steps):
+        for k, a in enumerate(active):
+            if not a:
+                continue
+            s, gs = self.state[k], self.g_star[k]
+            t0, t1 = s["t"], s["t"] + steps
+            if s["g"] > gs:
+                s["U"] = 0.02 * (s["g"] - gs) / gs + 2e-3
+                s["X"] += s["U"] * steps
+            elif k in self.creepers:
+                s["U"] = 1e-4
+                s["X"] += s["U"] * steps
+            else:
+                U0, T = 1e-4, 3000.0
+                s["X"] += U0 * T * (math.exp(-t0 / T) - math.exp(-t1 / T))
+                s["U"] = U0 * math.exp(-t1 / T)
+            s["t"] = t1
+
+    def monitors(self):
+        out = []
+        for k, s in enumerate(self.state):
+            nx = self.p[k]["nx"]
+            x = self.x0[k] + s["X"]
+            M = 1000.0
+            bad = 1.0 if s["g"] > self.g_bad[k] else 0.0
+            out.append({"mass": (M, 5000.0), "momentum": (0.0, 0.0), "oil_flux": M * s["U"],
+                        "oil_cos": M * math.cos(2 * math.pi * x / nx),
+                        "oil_sin": M * math.sin(2 * math.pi * x / nx), "bad_nodes": bad})
+        return out
+
+
+def _problems(g_stars, span=30.0, max_steps=200000):
+    cfgs, plain = [], []
+    for k, gs in enumerate(g_stars):
+        cfg = synth.config_channel(lam=64 * (1 + k % 3), theta=90.0)
+        cfgs.append(binding.cp_problem(cfg, gs / span, gs * span, sigma=0.161, rho_bar=1.03,
+                                       equil_steps=0, max_steps=max_steps))
+        plain.append(dict(nx=cfg["nx"], lam=cfg["lam"], h0=cfg["h0"], a=cfg["a"],
+                          tau_w=cfg["tau"][1], g_lo=gs / span, g_hi=gs * span,
+                          max_steps=max_steps, sigma=0.161, rho_bar=1.03))
+    return cfgs, plain
+
+
+def test_bisection_brackets_the_known_threshold():
+    g_stars = [3.3e-5, 1.1e-6, 7.7e-4, 2.0e-5]
+    probs, plain = _problems(g_stars)
+    res = binding.lbm_cp_drive(FakeEngine(plain, g_stars), probs, binding.cp_options())
+    for r, gs in zip(res, g_stars):
+        assert r["g_lo"] <= gs <= r["g_hi"]
+        assert (r["g_hi"] - r["g_lo"]) / r["g_lo"] <= 0.005
+        assert abs(r["g_crit"] / gs - 1) < 0.005
+        assert r["flags"] == 0
+        # log2(ln(900) / 0.005) ~ 10.4 halvings of the log-bracket
+        assert 10 <= r["probes"] <= 12
+    assert res[0]["bo_crit"] == pytest.approx(1.03 * res[0]["g_crit"] * 256 * (8 - 4) / 0.161)
+
+
+def test_library_driver_matches_the_oracle_driver():
+    """Same engine, same rules: both drivers probe the same g sequence."""
+    g_stars = [3.3e-5, 1.1e-6, 7.7e-4]
+    probs, plain = _problems(g_stars)
+    history = [[] for _ in g_stars]
+
+    class Recording(FakeEngine):
+        def begin_probe(self, k, g):
+            history[k].append(g)
+            super().begin_probe(k, g)
+
+    lib = binding.lbm_cp_drive(Recording(plain, g_stars), probs, binding.cp_options())
+    ref = odrv.solve(FakeEngine(plain, g_stars), plain)
+    for k in range(len(g_stars)):
+        assert len(history[k]) == len(ref[k]["history"])
+        for a, b in zip(history[k], ref[k]["history"]):
+            assert a == pytest.approx(b, rel=1e-12)
+        assert lib[k]["g_crit"] == pytest.approx(ref[k]["g_crit"], rel=1e-12)
+        assert lib[k]["probes"] == ref[k]["probes"] and lib[k]["flags"] == ref[k]["flags"]
+
+
+def test_bracket_verification_widens_a_wrong_bracket():
+    g_stars = [5e-5, 5e-5]
+    probs, plain = _problems(g_stars, span=1.0)
+    probs[0].g_lo, probs[0].g_hi = 2e-4, 4e-4     # threshold below the bracket
+    probs[1].g_lo, probs[1].g_hi = 1e-6, 2e-6     # threshold above the bracket
+    plain[0].update(g_lo=2e-4, g_hi=4e-4)
+    plain[1].update(g_lo=1e-6, g_hi=2e-6)
+    opts = binding.cp_options(verify_bracket=1)
+    res = binding.lbm_cp_drive(FakeEngine(plain, g_stars), probs, opts)
+    ref = odrv.solve(FakeEngine(plain, g_stars), plain, verify_bracket=1)
+    for r, o in zip(res, ref):
+        assert r["flags"] & binding._lib.CP_WIDENED
+        assert r["g_lo"] <= 5e-5 <= r["g_hi"]
+        assert r["g_crit"] == pytest.approx(o["g_crit"], rel=1e-12)
+
+
+def test_unstable_and_undecided_probes_are_flagged():
+    g_stars = [2e-5, 2e-5]
+    probs, plain = _problems(g_stars, max_steps=60000)
+    eng = FakeEngine(plain, g_stars, g_bad=[1e-4, math.inf], creepers=[1])
+    res = binding.lbm_cp_drive(eng, probs, binding.cp_options())
+    assert res[0]["flags"] & binding._lib.CP_UNSTABLE
+    assert res[0]["g_lo"] <= 2e-5 <= res[0]["g_hi"]
+    assert res[1]["flags"] & binding._lib.CP_UNDECIDED
+
+
+def test_driver_rejects_bad_problems():
+    probs, plain = _problems([1e-5])
+    probs[0].g_lo = 0.0
+    with pytest.raises(binding._lib.LbmError):
+        binding.lbm_cp_drive(FakeEngine(plain, [1e-5]), probs, binding.cp_options())
