@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2-comp MLUPS & % HBM roofline; critical-pressure solves/hr batched vs plain"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"f32": 144, "f16": 72, "bf16": 72}
+BYTES_PER_NODE = {"f32": 144, "f16": 80, "bf16": 80}
 
 
 def workload(name):

@@ -68,7 +68,8 @@ class LbmCpOptions(ctypes.Structure):
                 ("creep_frac", ctypes.c_double), ("still_frac", ctypes.c_double),
                 ("chunk_steps", ctypes.c_int32), ("still_chunks", ctypes.c_int32),
                 ("max_probes", ctypes.c_int32), ("verify_bracket", ctypes.c_int32),
-                ("min_steps", ctypes.c_int64)]
+                ("min_steps", ctypes.c_int64), ("storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class LbmCpResult(ctypes.Structure):

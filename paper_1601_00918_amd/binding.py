@@ -196,6 +196,8 @@ def cp_options(**overrides):
     o = LbmCpOptions()
     _lib.load().lbm_cp_default_options(ctypes.byref(o))
     for k, v in overrides.items():
+        if k == "storage" and isinstance(v, str):
+            v = _STORAGE[v]
         setattr(o, k, v)
     return o
 

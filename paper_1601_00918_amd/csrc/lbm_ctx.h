@@ -17,7 +17,7 @@ struct InstHost {
     int kind;
     int nx, ny;
     int pitch;
-    int64_t elems;  // population elements of this instance (18 * pitch * ny, padded)
+    int64_t elems;  // elements of this instance in one buffer (rstride * ny)
     int64_t f_off;
     std::vector<Col> cols;  // per column fluid run
 };
@@ -26,7 +26,7 @@ struct InstHost {
 struct Layout {
     size_t buf_bytes;  // one population buffer
     size_t off_buf[2], off_snap, off_inst, off_items, off_cols, off_partial, off_mon,
-        off_first, off_count, off_stage, total;
+        off_first, off_count, off_stage, off_seed, total;
     int64_t n_items_max;
     int64_t max_nodes;
 };
@@ -48,7 +48,8 @@ struct lbm_ctx {
     std::vector<int32_t> item_first, item_count;
     Layout L{};
     char* ws = nullptr;
-    float* buf[2] = {nullptr, nullptr};
+    char* buf[2] = {nullptr, nullptr};  // population buffers (element size es)
+    size_t es = 4;
     InstDev* inst_d = nullptr;
     Item* items_d = nullptr;
     Col* cols_d = nullptr;
@@ -57,6 +58,7 @@ struct lbm_ctx {
     int32_t* first_d = nullptr;
     int32_t* count_d = nullptr;
     double* stage_d = nullptr;
+    uint32_t* seed_d = nullptr;  // step number read by captured graphs
     hipStream_t stream = nullptr;
     int cur = 0;
     int64_t t = 0;
@@ -70,7 +72,7 @@ struct lbm_ctx {
     // follow `cur`; an inactive one stays where it was when it stopped.
     std::vector<int> ipar;
     // Snapshot buffer (optional, LBM_OPT_SNAPSHOT).
-    float* snap = nullptr;
+    char* snap = nullptr;
     int64_t snap_t = -1;
     // Cached graph of kGraphSteps step launches (non-null streams only).
     hipGraphExec_t graph = nullptr;

@@ -73,7 +73,8 @@ lbm_status check_options(const lbm_cp_options& o)
 {
     if (!(o.rel_tol > 0.0) || !(o.move_frac > 0.0) || !(o.creep_frac > 0.0) ||
         !(o.still_frac > 0.0) || o.chunk_steps < 2 || (o.chunk_steps & 1) || o.still_chunks < 1 ||
-        o.max_probes < 1 || o.min_steps < 0)
+        o.max_probes < 1 || o.min_steps < 0 || o.storage < LBM_STORE_F32 ||
+        o.storage > LBM_STORE_BF16)
         return fail(LBM_ERR_INVALID, "invalid critical-pressure options");
     return LBM_OK;
 }
@@ -331,7 +332,7 @@ lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
         inits[k] = probs[k].init;
     }
     HipEngine eng;
-    e = lbm_init(geoms.data(), fluids.data(), inits.data(), n, LBM_STORE_F32 | LBM_OPT_SNAPSHOT,
+    e = lbm_init(geoms.data(), fluids.data(), inits.data(), n, o.storage | LBM_OPT_SNAPSHOT,
                  device_workspace, workspace_bytes, hip_stream, &eng.ctx);
     if (e != LBM_OK)
         return e;

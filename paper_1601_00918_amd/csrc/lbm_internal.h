@@ -7,15 +7,18 @@
 
 namespace lbm {
 
-// One instance as the kernels see it.  The 18 population rows (species s,
-// direction i) of lattice row y are stored next to each other:
-//   buf[f_off + y * rstride + (s * 9 + i) * pitch + x],  rstride = 18 * pitch,
-// so one lattice row of one instance is a single contiguous block.
+// One instance as the kernels see it.  A lattice row y is one contiguous
+// block of planes; plane i holds, for every column x, the pair (oil, water)
+// of direction i:
+//   pair (i, x) of row y at element f_off + y * rstride + 2 * (i * pitch + x),
+// in units of one species value (4 bytes in FP32, 2 in the 16-bit formats).
+// FP32 has 9 planes (rstride = 18 * pitch).  The 16-bit formats add a tenth
+// plane with the node reference densities (rstride = 20 * pitch).
 struct InstDev {
     int64_t f_off;      // element offset of the instance in the population buffers
     int32_t nx, ny;
     int32_t pitch;      // elements per population row (>= nx, multiple of 64)
-    int32_t rstride;    // elements per lattice row (18 * pitch)
+    int32_t rstride;    // species values per lattice row (18 or 20 times pitch)
     int32_t periodic_y; // 1: box geometry, every node fluid, rows wrap
     int32_t col_off;    // offset of this instance's column table entries
     float tau_h[2];     // tau^a - 1/2 (= nu^a / T0, Eqs. 4-5)
@@ -24,7 +27,6 @@ struct InstDev {
     float g[2];         // body acceleration
     float pad1;
     double Gd;          // G in double (pressure export)
-    double enc_ref[2];  // reserved for deviation storage
 };
 
 // A work item: one workgroup advances the columns x0..x0+BX-1 of instance
@@ -61,13 +63,18 @@ constexpr int kMonWidth = 8;
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the launch
 // status.
-hipError_t launch_step(int bx, int mode, const float* fin, float* fout, const InstDev* insts,
-                       const Item* items, int item_base, int n_items, const Col* cols,
-                       double* partial, double* stage, hipStream_t stream);
+// The rounding sequence of the 16-bit formats is keyed by the step number
+// seed + (seed_dev ? *seed_dev : 0) (seed_dev lets a captured graph take the
+// step number from device memory; see launch_set_seed).
+hipError_t launch_step(int storage, int bx, int mode, const void* fin, void* fout,
+                       const InstDev* insts, const Item* items, int item_base, int n_items,
+                       const Col* cols, double* partial, double* stage, uint32_t seed,
+                       const uint32_t* seed_dev, hipStream_t stream);
+hipError_t launch_set_seed(uint32_t* seed_dev, uint32_t value, hipStream_t stream);
 hipError_t launch_mon_reduce(const double* partial, const int32_t* item_first,
                              const int32_t* item_count, int n_inst, double* mon,
                              hipStream_t stream);
-hipError_t launch_init(float* A, const InstDev* insts, int inst, const Col* cols, int nx,
-                       int ny, const InitDev& ini, hipStream_t stream);
+hipError_t launch_init(int storage, void* A, const InstDev* insts, int inst, const Col* cols,
+                       int nx, int ny, const InitDev& ini, hipStream_t stream);
 
 }  // namespace lbm

@@ -5,11 +5,12 @@
 // A step is then a pure "pull": node x gathers f_i(x, t) = f*_i(x - c_i) (or,
 // when x - c_i is solid, the half-way bounce-back value f*_opp(i)(x)), which
 // are the populations of Eq. 1's left side at time t, collides them and writes
-// its own f*(x, t) to buffer B at its own address.  Reads are coalesced
-// (neighbouring lanes read neighbouring addresses, shifted by at most one
-// element) and writes are aligned; every population is read once and written
-// once per step: 2 species x 9 directions x (4 B read + 4 B write) = 144 B per
-// fluid node.
+// its own f*(x, t) to buffer B at its own address.  The two species of one
+// (node, direction) are stored as one pair, so a node reads 9 pairs and
+// writes 9 pairs.  Reads are coalesced (neighbouring lanes read neighbouring
+// addresses, shifted by at most one pair) and writes are aligned; every
+// population is read once and written once per step: 2 species x 9
+// directions x (4 B read + 4 B write) = 144 B per fluid node in FP32.
 //
 // Tiling.  A workgroup of BX threads owns BX consecutive columns of one
 // instance and marches along a strip of rows, one row per iteration
@@ -21,11 +22,12 @@
 // the momentum flux Pi, per species), publishes its densities in an LDS ring
 // of four rows, and after one barrier collides row r from the moments it kept
 // in registers.  The two columns left and right of the workgroup are pulled by
-// lanes of wave 0 (one population per lane) and reduced in the same order as a
+// lanes of wave 0 (one direction per lane) and reduced in the same order as a
 // node's own density, so a density is bitwise the same whichever workgroup
 // computes it.  Solid neighbours enter the ring as the wall potentials rho_s.
 #include "lbm_internal.h"
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 namespace lbm {
@@ -36,6 +38,184 @@ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // 36 * w_i: the D2Q9 weights are exact multiples of 1/36.
 constexpr float kW36[9] = {16.f, 4.f, 4.f, 4.f, 4.f, 1.f, 1.f, 1.f, 1.f};
+
+// 1 / (36 w_i): exact powers of two.
+constexpr float kInvW36[9] = {1.f / 16.f, 0.25f, 0.25f, 0.25f, 0.25f, 1.f, 1.f, 1.f, 1.f};
+
+// Population storage formats.  A lattice row of an instance is one block of
+// planes; plane i holds, for every column x, the pair (oil, water) of
+// direction i, so one load or store moves both species of one (node,
+// direction).  FP32 stores f_i itself (8-byte pairs, 9 planes).  The 16-bit
+// formats (binary16, bfloat16; 4-byte pairs) store the deviation
+// d_i = f*_i(y) / w_i - R(y) of the post-collision population from the
+// lattice weight times a reference density R(y) of the same node and
+// species, and R(y) itself, in binary16, in a tenth plane.  A slow creeping
+// flow changes a population by far less than one unit in the last place of a
+// 16-bit number per step; storing the deviation from the node's own density
+// leaves only the velocity and stress part to round, so the step's small
+// changes are kept.  The two species have bulk densities about 30 times
+// apart and each takes both values somewhere in the domain, which is why the
+// reference is per node rather than per species.  The encoder makes the
+// node's stored mass exact: d_1..d_8 are rounded to nearest even and d_0 takes
+// the remainder of rho - R - sum w_i d_i, rounded stochastically (unbiased,
+// independent from step to step), so per-node mass errors do not freeze into
+// a drift when the flow is steady.  The kernels work in populations scaled by
+// 36 (36 f_i = (36 w_i)(R + d_i)), so the weights are the exact factors 16,
+// 4 and 1; the regularized collision is linear in the moments and runs
+// unchanged on scaled values; the interaction constant, the wall potentials
+// and the FP64 monitors and exports take the scale into account.
+struct F16Tag {};
+struct BF16Tag {};
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Store;
+
+template <>
+struct Store<float> {
+    static constexpr uint32_t kBytes = 4;  // one species value
+    static constexpr uint32_t kPair = 8;   // one (oil, water) pair
+    static constexpr int kPlanes = 9;
+    static constexpr float kScale = 1.0f;
+    static constexpr bool kRef = false;
+    using Pair = f2v;
+    __device__ static Pair load(const char* p) { return *reinterpret_cast<const f2v*>(p); }
+    __device__ static void unpack(Pair v, float& a, float& b)
+    {
+        a = v.x;
+        b = v.y;
+    }
+    __device__ static void put(char* p, float a, float b)
+    {
+        f2v v;
+        v.x = a;
+        v.y = b;
+        __builtin_nontemporal_store(v, reinterpret_cast<f2v*>(p));
+    }
+};
+
+__device__ __forceinline__ void put32(char* p, uint32_t b)
+{
+    __builtin_nontemporal_store(b, reinterpret_cast<uint32_t*>(p));
+}
+
+__device__ __forceinline__ float h2f(uint32_t b)
+{
+    return __half2float(__ushort_as_half((unsigned short)b));
+}
+__device__ __forceinline__ uint32_t f2h_rn(float v) { return __half_as_ushort(__float2half_rn(v)); }
+
+template <>
+struct Store<F16Tag> {
+    static constexpr uint32_t kBytes = 2;
+    static constexpr uint32_t kPair = 4;
+    static constexpr int kPlanes = 10;
+    static constexpr float kScale = 36.0f;
+    static constexpr bool kRef = true;
+    using Pair = uint32_t;
+    __device__ static Pair load(const char* p) { return *reinterpret_cast<const uint32_t*>(p); }
+    __device__ static void unpack(Pair v, float& a, float& b)
+    {
+        a = h2f(v & 0xffffu);
+        b = h2f(v >> 16);
+    }
+    __device__ static float val(uint32_t b) { return h2f(b); }
+    __device__ static uint32_t rne(float v) { return f2h_rn(v); }
+    // Stochastic rounding to binary16: add uniform random bits below the
+    // target precision to the magnitude and truncate (exact conversion after).
+    __device__ static uint32_t sr(float v, uint32_t rnd)
+    {
+        const uint32_t u = __float_as_uint(v);
+        const uint32_t sign = u & 0x80000000u;
+        uint32_t a = u & 0x7fffffffu;
+        const int e = (int)(a >> 23) - 127;
+        if (e >= -14) {  // binary16 normal range: 13 bits below the last place
+            a = (a + (rnd & 0x1fffu)) & ~0x1fffu;
+        } else if (e >= -24) {  // subnormal: the last place is 2^-24
+            const uint32_t m = (1u << (uint32_t)(-1 - e)) - 1u;
+            a = (a + (rnd & m)) & ~m;
+        } else {  // below 2^-24: 0 or 2^-24 with probability |v| / 2^-24
+            a = (float)(rnd >> 8) * 0x1p-24f < __uint_as_float(a) * 0x1p24f ? 0x33800000u : 0u;
+        }
+        return f2h_rn(__uint_as_float(sign | a));
+    }
+};
+
+template <>
+struct Store<BF16Tag> {
+    static constexpr uint32_t kBytes = 2;
+    static constexpr uint32_t kPair = 4;
+    static constexpr int kPlanes = 10;
+    static constexpr float kScale = 36.0f;
+    static constexpr bool kRef = true;
+    using Pair = uint32_t;
+    __device__ static Pair load(const char* p) { return *reinterpret_cast<const uint32_t*>(p); }
+    __device__ static void unpack(Pair v, float& a, float& b)
+    {
+        a = __uint_as_float(v << 16);
+        b = __uint_as_float(v & 0xffff0000u);
+    }
+    __device__ static float val(uint32_t b) { return __uint_as_float(b << 16); }
+    // Round to nearest even (the deviations are finite by construction).
+    __device__ static uint32_t rne(float v)
+    {
+        const uint32_t u = __float_as_uint(v);
+        return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    }
+    __device__ static uint32_t sr(float v, uint32_t rnd)
+    {
+        return (__float_as_uint(v) + (rnd & 0xffffu)) >> 16;
+    }
+};
+
+// Integer hash (Wellons' "lowbias32", from his 2018 hash-prospector search):
+// a bijection of 32-bit integers with low bias, used as a counter-based
+// generator for the stochastic rounding bits.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Encode the scaled post-collision populations F[s][9] of both species at one
+// node (scaled densities rho36[s]) into the 16-bit deviation format and store
+// the 9 pairs and the reference pair.  plane: bytes between planes.
+template <typename S>
+__device__ __forceinline__ void encode_node(const float (&F)[2][9], const float (&rho36)[2],
+                                            const uint32_t (&rnd)[2], char* dst, uint32_t plane)
+{
+    uint32_t rb[2];
+    float R[2], msum[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rb[s] = f2h_rn(rho36[s] * (1.0f / 36.0f));
+        R[s] = h2f(rb[s]);
+        msum[s] = 0.0f;
+    }
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        uint32_t b[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            b[s] = S::rne(F[s][i] * kInvW36[i] - R[s]);
+            msum[s] += kW36[i] * S::val(b[s]);
+        }
+        put32(dst + i * plane, b[0] | (b[1] << 16));
+    }
+    // 36 R is exact (R has 11 significant bits); rho36 - 36 R is exact
+    // whenever the two are within a factor of two.
+    uint32_t b0[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+        b0[s] = S::sr(((rho36[s] - 36.0f * R[s]) - msum[s]) * (1.0f / 16.0f), rnd[s]);
+    put32(dst, b0[0] | (b0[1] << 16));
+    put32(dst + 9 * plane, rb[0] | (rb[1] << 16));
+}
 
 __device__ __forceinline__ int wrapi(int a, int n)
 {
@@ -56,6 +236,7 @@ __device__ __forceinline__ int dir_cy(int i)
 {
     return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
 }
+__device__ __forceinline__ float dir_w36(int i) { return i == 0 ? 16.f : (i <= 4 ? 4.f : 1.f); }
 __device__ __forceinline__ int dir_opp(int i)
 {
     return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
@@ -166,15 +347,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Byte offsets (relative to the instance's first element) of the 9 pulled
-// populations of species 0 at node (x, r); species 1 adds 9 * pitch elements.
-// rb[k] is the element offset (row index times rstride) of row r - 1 + k.
-// Where x - c_i is solid the half-way bounce-back source f*_opp(i)(x) is used
-// instead.  Instances are smaller than 4 GiB, so 32-bit offsets suffice.
-template <bool PY>
-__device__ __forceinline__ void pull_offsets(const InstDev& P, const int (&rb)[3], int r, int xm,
-                                             int x, int xp, const ColG& g, uint32_t (&off)[9])
+// Byte offsets (relative to the instance's first byte) of the 9 pulled
+// (oil, water) pairs at node (x, r).  rb[k] is the pair offset (row index
+// times the row stride in pairs) of row r - 1 + k.  Where x - c_i is solid the
+// half-way bounce-back source f*_opp(i)(x) is used instead (bit i of the
+// returned mask).  Instances are smaller than 4 GiB, so 32-bit offsets suffice.
+template <bool PY, uint32_t PB>
+__device__ __forceinline__ uint32_t pull_offsets(const InstDev& P, const int (&rb)[3], int r, int xm,
+                                                 int x, int xp, const ColG& g, uint32_t (&off)[9])
 {
+    uint32_t bb = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int cx = kCx[i], cy = kCy[i];
@@ -186,17 +368,20 @@ __device__ __forceinline__ void pull_offsets(const InstDev& P, const int (&rb)[3
             const int sy = r - cy;
             src_fluid = (sy >= cc.lo) & (sy <= cc.hi);
         }
-        const uint32_t o_src = 4u * ((uint32_t)(i * P.pitch) + (uint32_t)(srb + sx));
-        const uint32_t o_bb = 4u * ((uint32_t)(kOpp[i] * P.pitch) + (uint32_t)(rb[1] + x));
+        const uint32_t o_src = PB * ((uint32_t)(i * P.pitch) + (uint32_t)(srb + sx));
+        const uint32_t o_bb = PB * ((uint32_t)(kOpp[i] * P.pitch) + (uint32_t)(rb[1] + x));
         off[i] = src_fluid ? o_src : o_bb;
+        bb |= src_fluid ? 0u : (1u << i);
     }
+    return bb;
 }
 
-template <int BX, int MODE, bool PY>
-__device__ __forceinline__ void march(const float* __restrict__ fin, float* __restrict__ fout,
+template <int BX, int MODE, bool PY, typename T>
+__device__ __forceinline__ void march(const void* __restrict__ fin, void* __restrict__ fout,
                                       const InstDev& P, const Item& it, int item_idx,
                                       const Col* __restrict__ cols, double* __restrict__ partial,
-                                      double* __restrict__ stage, float (&ring)[4][2][BX + 2],
+                                      double* __restrict__ stage, uint32_t seed,
+                                      float (&ring)[4][2][BX + 2], float2* __restrict__ rref,
                                       double (&red)[BX / 64][kMonWidth])
 {
     const int tid = threadIdx.x;
@@ -204,31 +389,44 @@ __device__ __forceinline__ void march(const float* __restrict__ fin, float* __re
     const bool act = tid < wdt;
     const int x = it.x0 + (act ? tid : 0);
     const int xm = wrapi(x - 1, P.nx), xp = wrapi(x + 1, P.nx);
-    // Scalar base pointers; every lane adds a 32-bit byte offset.
-    const char* __restrict__ base0 = reinterpret_cast<const char*>(fin + P.f_off);
-    const char* __restrict__ base1 = base0 + 36 * P.pitch;  // species 1
-    char* __restrict__ obase = reinterpret_cast<char*>(fout + P.f_off);
-    const uint32_t sp = 36u * (uint32_t)P.pitch;  // species stride in bytes
+    using S = Store<T>;
+    using Pair = typename S::Pair;
+    constexpr uint32_t PB = S::kPair;
+    constexpr float SC = S::kScale;
+    constexpr int RW = BX + 4;  // reference ring row: columns x0 - 2 .. x0 + BX + 1
+    const int RS = P.rstride >> 1;  // row stride in pairs
+    const uint32_t plane = PB * (uint32_t)P.pitch;  // bytes between planes
+    const char* __restrict__ base = reinterpret_cast<const char*>(fin) + S::kBytes * P.f_off;
+    char* __restrict__ obase = reinterpret_cast<char*>(fout) + S::kBytes * P.f_off;
+    const float rs0 = SC * P.rho_s[0], rs1 = SC * P.rho_s[1];  // wall potentials (scaled)
+    const float G36 = P.G36 * (1.0f / SC);
     ColG g{};
     if (!PY) {
         g.m = cols[P.col_off + xm];
         g.c = cols[P.col_off + x];
         g.p = cols[P.col_off + xp];
     }
-    // Halo lanes of wave 0: lane 16 k + j, k = side * 2 + species, j = direction.
-    const int hk = (tid >> 4) & 3, hj = tid & 15;
-    const int hside = hk >> 1, hs = hk & 1;
-    const bool hlane = tid < 64 && hj < 9;
+    // Halo lanes of wave 0: lane 16 side + j pulls direction j of the column
+    // left (side 0) or right (side 1) of the workgroup.
+    const int hj = tid & 15, hside = (tid >> 4) & 1;
+    const bool hgrp = tid < 32;
+    const bool hlane = hgrp && hj < 9;
     const int hx = hside ? wrapi(it.x0 + wdt, P.nx) : wrapi(it.x0 - 1, P.nx);
     const int hxm = wrapi(hx - 1, P.nx), hxp = wrapi(hx + 1, P.nx);
     const int hd = hj < 9 ? hj : 0;
     const int hcx = dir_cx(hd), hcy = dir_cy(hd), hopp = dir_opp(hd);
     const int hsx = hcx == 1 ? hxm : (hcx == -1 ? hxp : hx);
     Col hgc{0, 0}, hgs{0, 0};
-    if (!PY && tid < 64) {
+    if (!PY && hgrp) {
         hgc = cols[P.col_off + hx];
         hgs = cols[P.col_off + hsx];
     }
+    // Reference-density lanes of wave 0 (16-bit formats): lanes 16 side + 9
+    // and + 10 load the reference pairs of the two columns beyond each side
+    // that halo pulls reach (ring columns 0, 1 and wdt + 2, wdt + 3).
+    const bool rlane = S::kRef && hgrp && (hj == 9 || hj == 10);
+    const int rcol = hside ? wdt + 2 + (hj - 9) : hj - 9;
+    const int rx = wrapi(it.x0 - 2 + rcol, P.nx);
 
     const int64_t n_nodes = (int64_t)P.nx * P.ny;
     double macc[kMonWidth];
@@ -243,41 +441,74 @@ __device__ __forceinline__ void march(const float* __restrict__ fin, float* __re
     auto node_fluid = [&](const Col& c, int rr) -> bool {
         return PY ? true : ((rr >= c.lo) & (rr <= c.hi));
     };
+    // Reference pair of node (xx, row q); rows outside a channel read as 0.
+    auto load_ref = [&](int q, int xx) -> uint32_t {
+        const int qq = row_of(q);
+        if (!PY && (qq < 0 || qq >= P.ny))
+            return 0u;
+        return *reinterpret_cast<const uint32_t*>(
+            base + PB * ((uint32_t)(qq * RS) + (uint32_t)(9 * P.pitch) + (uint32_t)xx));
+    };
+    auto put_ref = [&](int q, int col, uint32_t v) {
+        rref[(q & 3) * RW + col] = make_float2(h2f(v & 0xffffu), h2f(v >> 16));
+    };
 
-    // Issue the pulls of row r into raw / hraw (loads left in flight).
-    float raw[18];
-    float hraw = 0.0f;
-    bool fl_next = false, hfl_next = false;
+    // March direction: y0 < y1 marches up over rows y0 .. y1 - 1; y0 > y1
+    // marches down over rows y0 .. y1 + 1.  Row r is pulled in the iteration
+    // that collides row r - d; its decoding needs the reference densities of
+    // rows r - 1 .. r + 1, which enter the ring two rows ahead of the pulls.
+    const int d = it.y1 > it.y0 ? 1 : -1;
+
+    // Issue the pulls of row r (loads left in flight).
+    Pair rawp[9];
+    Pair hrawp{};
+    bool fl_next = false, hfl_next = false, hbb_next = false;
+    uint32_t bb_next = 0, rnext = 0, hrnext = 0;
     auto issue_row = [&](int r) {
         const int rr = row_of(r);
         int rb[3];
-        rb[0] = row_of(r - 1) * P.rstride;
-        rb[1] = rr * P.rstride;
-        rb[2] = row_of(r + 1) * P.rstride;
+        rb[0] = row_of(r - 1) * RS;
+        rb[1] = rr * RS;
+        rb[2] = row_of(r + 1) * RS;
         fl_next = act && node_fluid(g.c, rr);
         if (fl_next) {
             uint32_t off[9];
-            pull_offsets<PY>(P, rb, rr, xm, x, xp, g, off);
+            bb_next = pull_offsets<PY, PB>(P, rb, rr, xm, x, xp, g, off);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                raw[i] = *reinterpret_cast<const float*>(base0 + off[i]);
-                raw[9 + i] = *reinterpret_cast<const float*>(base1 + off[i]);
-            }
+            for (int i = 0; i < 9; ++i)
+                rawp[i] = S::load(base + off[i]);
         }
         hfl_next = node_fluid(hgc, rr);
         if (hlane && hfl_next) {
             const int srb = rb[1 - hcy];
             const bool src_fluid = PY ? true : (((rr - hcy) >= hgs.lo) & ((rr - hcy) <= hgs.hi));
-            const uint32_t o = src_fluid ? 4u * ((uint32_t)(hd * P.pitch) + (uint32_t)(srb + hsx))
-                                         : 4u * ((uint32_t)(hopp * P.pitch) + (uint32_t)(rb[1] + hx));
-            hraw = *reinterpret_cast<const float*>(base0 + o + (hs ? sp : 0u));
+            hbb_next = !src_fluid;
+            const uint32_t o = src_fluid ? PB * ((uint32_t)(hd * P.pitch) + (uint32_t)(srb + hsx))
+                                         : PB * ((uint32_t)(hopp * P.pitch) + (uint32_t)(rb[1] + hx));
+            hrawp = S::load(base + o);
+        }
+        if (S::kRef) {
+            const int q = r + 2 * d;
+            const bool need = d * (q - (it.y1 + d)) <= 0;
+            rnext = (act && need) ? load_ref(q, x) : 0u;
+            hrnext = (rlane && need) ? load_ref(q, rx) : 0u;
         }
     };
 
-    // March direction: y0 < y1 marches up over rows y0 .. y1 - 1; y0 > y1
-    // marches down over rows y0 .. y1 + 1.  Row r is pulled in the iteration
-    // that collides row r - d.
-    const int d = it.y1 > it.y0 ? 1 : -1;
+    if (S::kRef) {
+        // Reference densities of the rows around the first pulled row.
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int q = it.y0 - 2 * d + k * d;
+            if (act)
+                put_ref(q, tid + 2, load_ref(q, x));
+            if (rlane)
+                put_ref(q, rcol, load_ref(q, rx));
+        }
+        lds_barrier();
+    }
+    const uint32_t seed_h = lowbias32(seed);
+
     Mom prev[2], cur[2];
     bool prev_fluid = false;
     issue_row(it.y0 - d);
@@ -288,29 +519,68 @@ __device__ __forceinline__ void march(const float* __restrict__ fin, float* __re
         const bool fl = fl_next;
         const bool hfl = hfl_next;
         if (fl) {
+            float raw[18];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                S::unpack(rawp[i], raw[i], raw[9 + i]);
+            if (S::kRef) {
+                const uint32_t bbm = bb_next;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const bool bb = (bbm >> i) & 1u;
+                    const int sl = bb ? (r & 3) : ((r - kCy[i]) & 3);
+                    const int cl = bb ? tid + 2 : tid + 2 - kCx[i];
+                    const float2 R = rref[sl * RW + cl];
+                    raw[i] = kW36[i] * (R.x + raw[i]);
+                    raw[9 + i] = kW36[i] * (R.y + raw[9 + i]);
+                }
+            }
             cur[0] = moments9(raw);
             cur[1] = moments9(raw + 9);
             if (MODE == kExport && d * (r - it.y0) >= 0 && d * (it.y1 - r) > 0) {
                 const int64_t k = (int64_t)rr * P.nx + x;
 #pragma unroll
                 for (int i = 0; i < 18; ++i)
-                    stage[(int64_t)i * n_nodes + k] = (double)raw[i];
+                    stage[(int64_t)i * n_nodes + k] = (double)raw[i] / (double)SC;
             }
         }
         if (act) {
-            ring[r & 3][0][tid + 1] = fl ? cur[0].rho : P.rho_s[0];
-            ring[r & 3][1][tid + 1] = fl ? cur[1].rho : P.rho_s[1];
+            ring[r & 3][0][tid + 1] = fl ? cur[0].rho : rs0;
+            ring[r & 3][1][tid + 1] = fl ? cur[1].rho : rs1;
         }
         if (tid < 64) {
-            const float v = (hlane && hfl) ? hraw : 0.0f;
-            float q[9];
+            float v0 = 0.0f, v1 = 0.0f;
+            if (hlane && hfl) {
+                S::unpack(hrawp, v0, v1);
+                if (S::kRef) {
+                    const int ch = hside ? wdt + 2 : 1;
+                    const int sl = hbb_next ? (r & 3) : ((r - hcy) & 3);
+                    const int cl = hbb_next ? ch : ch - hcx;
+                    const float2 R = rref[sl * RW + cl];
+                    const float w = dir_w36(hd);
+                    v0 = w * (R.x + v0);
+                    v1 = w * (R.y + v1);
+                }
+            }
+            float q0[9], q1[9];
 #pragma unroll
-            for (int j = 0; j < 9; ++j)
-                q[j] = __shfl(v, (tid & ~15) + j, 64);
-            const float rh = rho9(q);
-            if (hj == 0)
-                ring[r & 3][hs][hside ? wdt + 1 : 0] =
-                    hfl ? rh : (hs ? P.rho_s[1] : P.rho_s[0]);
+            for (int j = 0; j < 9; ++j) {
+                q0[j] = __shfl(v0, (tid & ~15) + j, 64);
+                q1[j] = __shfl(v1, (tid & ~15) + j, 64);
+            }
+            const float rh0 = rho9(q0), rh1 = rho9(q1);
+            if (hgrp && hj == 0) {
+                const int col = hside ? wdt + 1 : 0;
+                ring[r & 3][0][col] = hfl ? rh0 : rs0;
+                ring[r & 3][1][col] = hfl ? rh1 : rs1;
+            }
+        }
+        if (S::kRef) {
+            // Reference row r + 2d (loaded with the pulls of row r).
+            if (act)
+                put_ref(r + 2 * d, tid + 2, rnext);
+            if (rlane)
+                put_ref(r + 2 * d, rcol, hrnext);
         }
         // ---- pulls of row r + d go out before the barrier -----------------
         if (r != it.y1)
@@ -342,33 +612,40 @@ __device__ __forceinline__ void march(const float* __restrict__ fin, float* __re
             const float om = 1.0f - __builtin_amdgcn_rcpf(taum);
 
             if (MODE == kStep || MODE == kStepMon) {
-                const uint32_t o = 4u * (uint32_t)(rrc * P.rstride + x);
+                float out[2][9];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const float vx = ux + P.G36 * sx[s] + P.g[0];
-                    const float vy = uy + P.G36 * sy[s] + P.g[1];
-                    float out[9];
-                    collide_species(prev[s], vx, vy, om, out);
+                    const float vx = ux + G36 * sx[s] + P.g[0];
+                    const float vy = uy + G36 * sy[s] + P.g[1];
+                    collide_species(prev[s], vx, vy, om, out[s]);
+                }
+                // Streaming stores: the populations are read back only by the
+                // next step, long after they would have left L2.
+                char* dst = obase + PB * ((uint32_t)(rrc * RS) + (uint32_t)x);
+                if constexpr (S::kRef) {
+                    const uint32_t key = ((uint32_t)(rrc * P.nx + x)) << 1;
+                    const uint32_t rnd[2] = {lowbias32(key ^ seed_h),
+                                             lowbias32((key | 1u) ^ seed_h)};
+                    const float rho36[2] = {ro, rw};
+                    encode_node<S>(out, rho36, rnd, dst, plane);
+                } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        // Streaming store: the populations are read back only by
-                        // the next step, long after they would have left L2.
-                        char* dst = obase + 4 * (s * 9 + i) * P.pitch;
-                        __builtin_nontemporal_store(out[i], reinterpret_cast<float*>(dst + o));
-                    }
+                    for (int i = 0; i < 9; ++i)
+                        S::put(dst + i * plane, out[0][i], out[1][i]);
                 }
             }
             if (MODE != kStep) {
                 // Physical quantities of the state at time t, evaluated in FP64
                 // from the node's FP32 moments and neighbour densities.
-                const double dro = ro, drw = rw, drho = dro + drw;
-                const double G36 = P.Gd / 36.0;
-                const double fxo = dro * (G36 * (double)sx[0] + (double)P.g[0]);
-                const double fyo = dro * (G36 * (double)sy[0] + (double)P.g[1]);
-                const double fxw = drw * (G36 * (double)sx[1] + (double)P.g[0]);
-                const double fyw = drw * (G36 * (double)sy[1] + (double)P.g[1]);
-                const double px = (double)prev[0].jx + (double)prev[1].jx + 0.5 * (fxo + fxw);
-                const double py = (double)prev[0].jy + (double)prev[1].jy + 0.5 * (fyo + fyw);
+                const double isc = 1.0 / (double)SC;
+                const double dro = ro * isc, drw = rw * isc, drho = dro + drw;
+                const double Gd36 = P.Gd / 36.0 * isc;
+                const double fxo = dro * (Gd36 * (double)sx[0] + (double)P.g[0]);
+                const double fyo = dro * (Gd36 * (double)sy[0] + (double)P.g[1]);
+                const double fxw = drw * (Gd36 * (double)sx[1] + (double)P.g[0]);
+                const double fyw = drw * (Gd36 * (double)sy[1] + (double)P.g[1]);
+                const double px = ((double)prev[0].jx + (double)prev[1].jx) * isc + 0.5 * (fxo + fxw);
+                const double py = ((double)prev[0].jy + (double)prev[1].jy) * isc + 0.5 * (fyo + fyw);
                 const double upx = px / drho, upy = py / drho;
                 if (MODE == kExport) {
                     const int64_t k = (int64_t)rrc * P.nx + x;
@@ -416,22 +693,32 @@ __device__ __forceinline__ void march(const float* __restrict__ fin, float* __re
     }
 }
 
-template <int BX, int MODE>
+template <int BX, int MODE, typename T>
 __global__ void __launch_bounds__(BX)
-step_kernel(const float* __restrict__ fin, float* __restrict__ fout,
+step_kernel(const void* __restrict__ fin, void* __restrict__ fout,
             const InstDev* __restrict__ insts, const Item* __restrict__ items, int item_base,
             const Col* __restrict__ cols, double* __restrict__ partial,
-            double* __restrict__ stage)
+            double* __restrict__ stage, uint32_t seed, const uint32_t* __restrict__ seed_dev)
 {
     __shared__ float ring[4][2][BX + 2];
+    __shared__ float2 rref[Store<T>::kRef ? 4 * (BX + 4) : 1];
     __shared__ double red[BX / 64][kMonWidth];
+    const uint32_t sd = seed + (seed_dev ? seed_dev[0] : 0u);
     const int item_idx = item_base + remap_xcd((int)blockIdx.x, (int)gridDim.x);
     const Item it = items[item_idx];
     const InstDev P = insts[it.inst];
     if (P.periodic_y)
-        march<BX, MODE, true>(fin, fout, P, it, item_idx, cols, partial, stage, ring, red);
+        march<BX, MODE, true, T>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring, rref,
+                                 red);
     else
-        march<BX, MODE, false>(fin, fout, P, it, item_idx, cols, partial, stage, ring, red);
+        march<BX, MODE, false, T>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
+                                  rref, red);
+}
+
+__global__ void set_seed_kernel(uint32_t* seed_dev, uint32_t v)
+{
+    if (threadIdx.x == 0)
+        seed_dev[0] = v;
 }
 
 __global__ void mon_reduce_kernel(const double* __restrict__ partial,
@@ -486,10 +773,14 @@ __device__ double init_density(const InitDev& ini, const InstDev& P, int s, int 
 
 // Rest equilibrium f_i = w_i rho0, placed where the first pull reads it: the
 // slot (x, i) is read by node x + c_i (direction i) when that node is fluid,
-// otherwise by node x itself after bounce-back (direction opp(i)).
-__global__ void init_kernel(float* __restrict__ A, const InstDev* __restrict__ insts, int inst,
+// otherwise by node x itself after bounce-back (direction opp(i)).  In the
+// 16-bit formats the slot holds rho0(reader) - R(x), rounded to nearest even,
+// with R(x) the binary16 value of rho0(x).
+template <typename T>
+__global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ insts, int inst,
                             const Col* __restrict__ cols, InitDev ini)
 {
+    using S = Store<T>;
     const InstDev P = insts[inst];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
@@ -504,6 +795,19 @@ __global__ void init_kernel(float* __restrict__ A, const InstDev* __restrict__ i
     };
     if (!fluid(x, y))
         return;
+    char* node = reinterpret_cast<char*>(A) +
+                 S::kBytes * (P.f_off + (int64_t)y * P.rstride) + S::kPair * (int64_t)x;
+    const int64_t plane = (int64_t)S::kPair * P.pitch;
+    float R[2] = {0.0f, 0.0f};
+    if constexpr (S::kRef) {
+        uint32_t rpair = 0;
+        for (int s = 0; s < 2; ++s) {
+            const uint32_t rb = f2h_rn((float)init_density(ini, P, s, x, y));
+            R[s] = h2f(rb);
+            rpair |= rb << (16 * s);
+        }
+        *reinterpret_cast<uint32_t*>(node + 9 * plane) = rpair;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const double w = kW36[i] / 36.0;
@@ -515,36 +819,43 @@ __global__ void init_kernel(float* __restrict__ A, const InstDev* __restrict__ i
             xr = x;
             yr = y;
         }
-        for (int s = 0; s < 2; ++s) {
-            const double rho0 = init_density(ini, P, s, xr, yr);
-            A[P.f_off + (int64_t)y * P.rstride + (int64_t)(s * 9 + i) * P.pitch + x] =
-                (float)(w * rho0);
-        }
+        const double rho_o = init_density(ini, P, 0, xr, yr);
+        const double rho_w = init_density(ini, P, 1, xr, yr);
+        if constexpr (S::kRef)
+            *reinterpret_cast<uint32_t*>(node + i * plane) =
+                S::rne((float)(rho_o - (double)R[0])) |
+                (S::rne((float)(rho_w - (double)R[1])) << 16);
+        else
+            S::put(node + i * plane, (float)(w * rho_o), (float)(w * rho_w));
     }
 }
 
-template <int BX>
-hipError_t launch_step_bx(int mode, const float* fin, float* fout, const InstDev* insts,
+template <int BX, typename T>
+hipError_t launch_step_bx(int mode, const void* fin, void* fout, const InstDev* insts,
                           const Item* items, int item_base, int n_items, const Col* cols,
-                          double* partial, double* stage, hipStream_t stream)
+                          double* partial, double* stage, uint32_t seed,
+                          const uint32_t* seed_dev, hipStream_t stream)
 {
     const dim3 grid(n_items), block(BX);
     switch (mode) {
     case kStep:
-        step_kernel<BX, kStep><<<grid, block, 0, stream>>>(fin, fout, insts, items, item_base,
-                                                           cols, partial, stage);
+        step_kernel<BX, kStep, T><<<grid, block, 0, stream>>>(fin, fout, insts, items, item_base,
+                                                              cols, partial, stage, seed, seed_dev);
         break;
     case kStepMon:
-        step_kernel<BX, kStepMon><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                              item_base, cols, partial, stage);
+        step_kernel<BX, kStepMon, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
+                                                                 item_base, cols, partial, stage,
+                                                                 seed, seed_dev);
         break;
     case kMonOnly:
-        step_kernel<BX, kMonOnly><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                              item_base, cols, partial, stage);
+        step_kernel<BX, kMonOnly, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
+                                                                 item_base, cols, partial, stage,
+                                                                 seed, seed_dev);
         break;
     case kExport:
-        step_kernel<BX, kExport><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                             item_base, cols, partial, stage);
+        step_kernel<BX, kExport, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
+                                                                item_base, cols, partial, stage,
+                                                                seed, seed_dev);
         break;
     default:
         return hipErrorInvalidValue;
@@ -552,27 +863,55 @@ hipError_t launch_step_bx(int mode, const float* fin, float* fout, const InstDev
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_step(int bx, int mode, const float* fin, float* fout, const InstDev* insts,
-                       const Item* items, int item_base, int n_items, const Col* cols,
-                       double* partial, double* stage, hipStream_t stream)
+template <typename T>
+hipError_t launch_step_t(int bx, int mode, const void* fin, void* fout, const InstDev* insts,
+                         const Item* items, int item_base, int n_items, const Col* cols,
+                         double* partial, double* stage, uint32_t seed, const uint32_t* seed_dev,
+                         hipStream_t stream)
 {
-    if (n_items <= 0)
-        return hipSuccess;
     switch (bx) {
     case 64:
-        return launch_step_bx<64>(mode, fin, fout, insts, items, item_base, n_items, cols,
-                                  partial, stage, stream);
+        return launch_step_bx<64, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+                                     partial, stage, seed, seed_dev, stream);
     case 128:
-        return launch_step_bx<128>(mode, fin, fout, insts, items, item_base, n_items, cols,
-                                   partial, stage, stream);
+        return launch_step_bx<128, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+                                      partial, stage, seed, seed_dev, stream);
     case 256:
-        return launch_step_bx<256>(mode, fin, fout, insts, items, item_base, n_items, cols,
-                                   partial, stage, stream);
+        return launch_step_bx<256, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+                                      partial, stage, seed, seed_dev, stream);
     default:
         return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+hipError_t launch_step(int storage, int bx, int mode, const void* fin, void* fout,
+                       const InstDev* insts, const Item* items, int item_base, int n_items,
+                       const Col* cols, double* partial, double* stage, uint32_t seed,
+                       const uint32_t* seed_dev, hipStream_t stream)
+{
+    if (n_items <= 0)
+        return hipSuccess;
+    switch (storage) {
+    case 0:
+        return launch_step_t<float>(bx, mode, fin, fout, insts, items, item_base, n_items, cols,
+                                    partial, stage, seed, seed_dev, stream);
+    case 1:
+        return launch_step_t<F16Tag>(bx, mode, fin, fout, insts, items, item_base, n_items, cols,
+                                     partial, stage, seed, seed_dev, stream);
+    case 2:
+        return launch_step_t<BF16Tag>(bx, mode, fin, fout, insts, items, item_base, n_items,
+                                      cols, partial, stage, seed, seed_dev, stream);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_set_seed(uint32_t* seed_dev, uint32_t value, hipStream_t stream)
+{
+    set_seed_kernel<<<dim3(1), dim3(64), 0, stream>>>(seed_dev, value);
+    return hipGetLastError();
 }
 
 hipError_t launch_mon_reduce(const double* partial, const int32_t* item_first,
@@ -586,13 +925,25 @@ hipError_t launch_mon_reduce(const double* partial, const int32_t* item_first,
     return hipGetLastError();
 }
 
-hipError_t launch_init(float* A, const InstDev* insts, int inst, const Col* cols, int nx,
-                       int ny, const InitDev& ini, hipStream_t stream)
+hipError_t launch_init(int storage, void* A, const InstDev* insts, int inst, const Col* cols,
+                       int nx, int ny, const InitDev& ini, hipStream_t stream)
 {
     if (ini.kind < 0 || ini.kind > 3)
         return hipErrorInvalidValue;
     const dim3 block(256), grid((nx + 255) / 256, ny);
-    init_kernel<<<grid, block, 0, stream>>>(A, insts, inst, cols, ini);
+    switch (storage) {
+    case 0:
+        init_kernel<float><<<grid, block, 0, stream>>>(A, insts, inst, cols, ini);
+        break;
+    case 1:
+        init_kernel<F16Tag><<<grid, block, 0, stream>>>(A, insts, inst, cols, ini);
+        break;
+    case 2:
+        init_kernel<BF16Tag><<<grid, block, 0, stream>>>(A, insts, inst, cols, ini);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -145,10 +145,17 @@ lbm_status check_fluid(const lbm_fluid& f)
 
 int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
 
-// Elements of one instance in one population buffer.
-int64_t inst_elems(int nx, int ny) { return (int64_t)18 * pitch_of(nx) * ny; }
-
 size_t elem_size(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
+
+// Elements per lattice row and pitch: 18 population rows, plus (16-bit
+// formats) the row of reference-density pairs.
+int row_planes(int storage) { return storage == LBM_STORE_F32 ? 18 : 20; }
+
+// Elements of one instance in one population buffer.
+int64_t inst_elems(int nx, int ny, int storage)
+{
+    return (int64_t)row_planes(storage) * pitch_of(nx) * ny;
+}
 
 // Upper bound on the number of work items for any supported tiling.
 int64_t max_items(const lbm_geom& g)
@@ -166,7 +173,7 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
     L.max_nodes = 0;
     for (int k = 0; k < n_inst; ++k) {
         const lbm_geom& g = geoms[k];
-        elems += inst_elems(g.nx, g.ny);
+        elems += inst_elems(g.nx, g.ny, storage);
         ncols += g.nx;
         L.n_items_max += max_items(g);
         L.max_nodes = std::max<int64_t>(L.max_nodes, (int64_t)g.nx * g.ny);
@@ -196,6 +203,8 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
     o = align_up(o + sizeof(int32_t) * n_inst, kAlign);
     L.off_stage = o;
     o = align_up(o + sizeof(double) * kExportFields * L.max_nodes, kAlign);
+    L.off_seed = o;
+    o = align_up(o + sizeof(uint32_t), kAlign);
     L.total = o;
     return L;
 }
@@ -205,7 +214,7 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
 lbm_ctx::~lbm_ctx()
 {
     if (graph)
-        hipGraphExecDestroy(graph);
+        (void)hipGraphExecDestroy(graph);
 }
 
 namespace {
@@ -301,8 +310,8 @@ lbm_status sync_instance(lbm_ctx* c, int k)
     if (c->ipar[k] == c->cur)
         return LBM_OK;
     const InstHost& h = c->ih[k];
-    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + h.f_off, c->buf[c->ipar[k]] + h.f_off,
-                           sizeof(float) * h.elems, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + c->es * h.f_off, c->buf[c->ipar[k]] + c->es * h.f_off,
+                           c->es * h.elems, hipMemcpyDeviceToDevice, c->stream));
     c->ipar[k] = c->cur;
     return LBM_OK;
 }
@@ -317,11 +326,12 @@ lbm_status sync_all(lbm_ctx* c)
     return LBM_OK;
 }
 
-lbm_status run_mode(lbm_ctx* c, int mode, int item_base, int n_items)
+lbm_status run_mode(lbm_ctx* c, int mode, int item_base, int n_items, uint32_t seed = 0,
+                    const uint32_t* seed_dev = nullptr)
 {
-    hipError_t e = launch_step(c->bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1], c->inst_d,
-                               c->items_d, item_base, n_items, c->cols_d, c->partial_d,
-                               c->stage_d, c->stream);
+    hipError_t e = launch_step(c->storage, c->bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1],
+                               c->inst_d, c->items_d, item_base, n_items, c->cols_d,
+                               c->partial_d, c->stage_d, seed, seed_dev, c->stream);
     if (e != hipSuccess)
         return fail(LBM_ERR_DEVICE, "step launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
@@ -340,7 +350,7 @@ lbm_status lbm_required_bytes(const lbm_geom* geoms, int32_t n_inst, int32_t sto
 {
     if (!geoms || n_inst < 1 || !bytes)
         return fail(LBM_ERR_INVALID, "lbm_required_bytes: null argument or n_inst < 1");
-    if ((storage & 0xff) != LBM_STORE_F32 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
+    if ((storage & 0xff) > LBM_STORE_BF16 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
         return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
     for (int k = 0; k < n_inst; ++k) {
         lbm_status st = check_geom(geoms[k]);
@@ -361,7 +371,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     *out = nullptr;
     if (!geoms || !fluids || !inits || n_inst < 1 || !device_workspace)
         return fail(LBM_ERR_INVALID, "lbm_init: null argument or n_inst < 1");
-    if ((storage & 0xff) != LBM_STORE_F32 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
+    if ((storage & 0xff) > LBM_STORE_BF16 || (storage & ~(0xff | LBM_OPT_SNAPSHOT)))
         return fail(LBM_ERR_UNSUPPORTED, "storage %d not supported", storage);
     if ((uintptr_t)device_workspace % kAlign)
         return fail(LBM_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
@@ -395,14 +405,15 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     c->n_inst = n_inst;
     c->storage = storage & 0xff;
     if (storage & LBM_OPT_SNAPSHOT)
-        c->snap = (float*)((char*)device_workspace + L.off_snap);
+        c->snap = (char*)device_workspace + L.off_snap;
     c->active.assign(n_inst, 1);
     c->ipar.assign(n_inst, 0);
     c->L = L;
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char*)device_workspace;
-    c->buf[0] = (float*)(c->ws + L.off_buf[0]);
-    c->buf[1] = (float*)(c->ws + L.off_buf[1]);
+    c->buf[0] = c->ws + L.off_buf[0];
+    c->buf[1] = c->ws + L.off_buf[1];
+    c->es = elem_size(storage & 0xff);
     c->inst_d = (InstDev*)(c->ws + L.off_inst);
     c->items_d = (Item*)(c->ws + L.off_items);
     c->cols_d = (Col*)(c->ws + L.off_cols);
@@ -411,6 +422,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     c->first_d = (int32_t*)(c->ws + L.off_first);
     c->count_d = (int32_t*)(c->ws + L.off_count);
     c->stage_d = (double*)(c->ws + L.off_stage);
+    c->seed_d = (uint32_t*)(c->ws + L.off_seed);
 
     // Instances, column tables.
     c->ih.resize(n_inst);
@@ -430,14 +442,14 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         h.nx = g.nx;
         h.ny = g.ny;
         h.pitch = pitch_of(g.nx);
-        h.elems = inst_elems(g.nx, g.ny);
+        h.elems = inst_elems(g.nx, g.ny, storage & 0xff);
         h.f_off = f_off;
         f_off += h.elems;
         max_nx = std::max(max_nx, g.nx);
         InstDev& d = c->idv[k];
         std::memset(&d, 0, sizeof d);
         d.f_off = h.f_off;
-        d.rstride = 18 * h.pitch;
+        d.rstride = row_planes(storage & 0xff) * h.pitch;
         d.nx = g.nx;
         d.ny = g.ny;
         d.pitch = h.pitch;
@@ -492,7 +504,8 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
             }
         ini.first_row = first;
         ini.last_row = last;
-        if ((e = launch_init(c->buf[0], c->inst_d, k, c->cols_d, h.nx, h.ny, ini, c->stream)) !=
+        if ((e = launch_init(c->storage, c->buf[0], c->inst_d, k, c->cols_d, h.nx, h.ny, ini,
+                             c->stream)) !=
             hipSuccess)
             return bail(fail(LBM_ERR_DEVICE, "init launch failed: %s", hipGetErrorString(e)));
     }
@@ -504,10 +517,16 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     return LBM_OK;
 }
 
-static lbm_status step_direct(lbm_ctx* c, int64_t nsteps)
+// Enqueue nsteps step launches.  The rounding sequence of the 16-bit formats
+// is keyed by the step number: passed as an argument, or, inside a captured
+// graph, as the offset k from the value in seed_d that is set before every
+// replay.
+static lbm_status step_direct(lbm_ctx* c, int64_t nsteps, bool in_graph = false)
 {
     for (int64_t k = 0; k < nsteps; ++k) {
-        lbm_status st = run_mode(c, kStep, (int)c->L.n_items_max, c->n_active_items);
+        const uint32_t seed = in_graph ? (uint32_t)k : (uint32_t)c->t;
+        lbm_status st = run_mode(c, kStep, (int)c->L.n_items_max, c->n_active_items, seed,
+                                 in_graph ? c->seed_d : nullptr);
         if (st != LBM_OK)
             return st;
         c->cur ^= 1;
@@ -523,26 +542,26 @@ static lbm_status ensure_graph(lbm_ctx* c)
     if (c->graph && !c->graph_dirty && c->graph_cur == c->cur)
         return LBM_OK;
     if (c->graph) {
-        hipGraphExecDestroy(c->graph);
+        (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
     }
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     const int cur0 = c->cur;
     const int64_t t0 = c->t;
-    lbm_status st = step_direct(c, kGraphSteps);
+    lbm_status st = step_direct(c, kGraphSteps, true);
     c->cur = cur0;
     c->t = t0;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != LBM_OK) {
         if (g)
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
         return st;
     }
     if (e != hipSuccess)
         return fail(LBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         c->graph = nullptr;
         return fail(LBM_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
@@ -567,6 +586,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps)
         if (st != LBM_OK)
             return st;
         for (; done + kGraphSteps <= nsteps; done += kGraphSteps) {
+            HIP_TRY(launch_set_seed(c->seed_d, (uint32_t)c->t, c->stream));
             HIP_TRY(hipGraphLaunch(c->graph, c->stream));
             c->t += kGraphSteps;
         }
@@ -620,8 +640,8 @@ lbm_status lbm_snapshot_restore(lbm_ctx* c, int32_t inst)
         return LBM_OK;
     }
     const InstHost& h = c->ih[inst];
-    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + h.f_off, c->snap + h.f_off,
-                           sizeof(float) * h.elems, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->buf[c->cur] + c->es * h.f_off, c->snap + c->es * h.f_off,
+                           c->es * h.elems, hipMemcpyDeviceToDevice, c->stream));
     c->ipar[inst] = c->cur;
     return LBM_OK;
 }

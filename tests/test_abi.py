@@ -50,9 +50,12 @@ def test_required_bytes_rejects_bad_geometry():
     assert e.value.status == 1 and "out of range" in str(e.value)
     with pytest.raises(_lib.LbmError):
         binding.lbm_required_bytes([_geom(h0=-1.0)])
-    with pytest.raises(_lib.LbmError) as e:
-        binding.lbm_required_bytes([_geom()], storage="bf16")
-    assert e.value.status == 6
+    g = [_geom()]
+    n = ctypes.c_size_t()
+    assert _lib.load().lbm_required_bytes(binding._arr(g, _lib.LbmGeom), 1, 7,
+                                          ctypes.byref(n)) == 6   # unknown storage format
+    half = binding.lbm_required_bytes(g, storage="f16")
+    assert half < binding.lbm_required_bytes(g) and binding.lbm_required_bytes(g, "bf16") == half
 
 
 def _try_init(geoms, fluids, inits, ws_bytes=1 << 30):
