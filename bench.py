@@ -77,6 +77,25 @@ def cpu_baseline(seconds):
                       "%d steps in %.1f s" % (nf, n, dt)}
 
 
+def measured_traffic(storage):
+    """HBM bytes per step launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter record of the 256-channel batch, scaled by the copy-kernel
+    calibration; None when the kernel source has changed since the counters
+    were taken or the format was not profiled."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "step_kernel_batch256_traffic.txt")
+    src = os.path.join(ROOT, "paper_1601_00918_amd", "csrc", "lbm_kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != h or storage not in rec:
+        return None
+    r = rec[storage]
+    return 1024.0 * (r["fetch_kib"] * rec["fetch_scale"] + r["write_kib"] * rec["write_scale"])
+
+
 def copy_calibration(steps, warmup, nbytes=2 << 30):
     """A plain device-to-device copy of nbytes (torch's copy kernel): the
     reference for the achievable HBM rate and for scaling the profiler's
@@ -147,6 +166,7 @@ def main():
 
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nf
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic(args.storage) if args.workload == "batch" else None
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -156,7 +176,11 @@ def main():
                    "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     # measured HBM bytes per launch over the same launch time
+                     "traffic": (round(traffic / (ms_per_step / 1e3) / 1e9, 1)
+                                 if traffic else None),
+                     "traffic_bytes_per_launch": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
