@@ -215,12 +215,41 @@ lbm_status lbm_fluid_mask(lbm_ctx* ctx, int32_t inst, uint8_t* mask);
 /*
  * Tiling of the step kernel: every instance is cut into work items of bx
  * consecutive columns (bx in {64, 128, 256}) by strip_rows rows (>= 4); one
- * workgroup of bx threads advances one item.  Results do not depend on the
- * tiling (bit for bit).  Synchronises the stream.
+ * workgroup of bx threads advances one item.  Instances of different bx run
+ * as separate launches within a step.  Results do not depend on the tiling
+ * (bit for bit).  These calls synchronise the stream.
+ * lbm_set_tiling sets every instance; lbm_get_tiling returns the values last
+ * set for every instance and the total number of work items.
  */
 lbm_status lbm_set_tiling(lbm_ctx* ctx, int32_t bx, int32_t strip_rows);
 lbm_status lbm_get_tiling(const lbm_ctx* ctx, int32_t* bx, int32_t* strip_rows,
                           int32_t* n_items);
+lbm_status lbm_set_instance_tiling(lbm_ctx* ctx, int32_t inst, int32_t bx, int32_t strip_rows);
+lbm_status lbm_get_instance_tiling(const lbm_ctx* ctx, int32_t inst, int32_t* bx,
+                                   int32_t* strip_rows);
+
+/* Outcome of lbm_autotune. */
+typedef struct {
+    int32_t buckets;    /* width classes tuned (active instances of equal nx) */
+    int32_t trials;     /* timed trials, warm-up included */
+    int64_t steps;      /* real steps advanced by the tuning */
+    double ms_before;   /* per-step time with the tiling on entry */
+    double ms_after;    /* per-step time with the chosen tiling */
+} lbm_tune_report;
+
+/*
+ * Autotuner of the tiling, per width class of the active instances (the
+ * channels of one wavelength share nx = 4 lambda): for the classes in
+ * decreasing order of fluid nodes, try bx in {64, 128, 256} (not wider than
+ * the instance) and strip_rows in {4, 8, 16, 32}, keep a candidate when the
+ * whole step gets at least 0.3 % faster, then move to the next class.  Each
+ * trial times steps_per_trial (>= 2) REAL steps of the run on ctx's stream
+ * with HIP events, through lbm_step (so graphs are used on non-null streams);
+ * the state advances by report->steps steps exactly as lbm_step would
+ * advance it, whatever tiling is chosen.  Call it during a phase whose steps
+ * are wanted anyway (an equilibration).  Synchronises; report may be NULL.
+ */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial, lbm_tune_report* report);
 
 /* Release the context (not the caller's workspace or stream). */
 void lbm_destroy(lbm_ctx* ctx);
@@ -268,7 +297,9 @@ typedef struct {
                                g_hi is moving */
     int64_t min_steps;      /* default 20000 */
     int32_t storage;        /* lbm_storage of the populations, default LBM_STORE_F32 */
-    int32_t reserved;
+    int32_t autotune;       /* 1: run lbm_autotune (32 steps per trial) at the start of
+                               the equilibration when every problem's equil_steps covers
+                               its steps; default 0 */
 } lbm_cp_options;
 
 enum {

@@ -24,10 +24,17 @@ EXPORTED = [
     "lbm_fluid_mask", "lbm_set_tiling", "lbm_get_tiling", "lbm_destroy", "lbm_set_active",
     "lbm_snapshot_save", "lbm_snapshot_restore", "lbm_cp_default_options",
     "lbm_cp_required_bytes", "lbm_critical_pressure", "lbm_cp_drive",
+    "lbm_set_instance_tiling", "lbm_get_instance_tiling", "lbm_autotune",
 ]
 
 OPT_SNAPSHOT = 0x100
 CP_UNDECIDED, CP_UNSTABLE, CP_WIDENED, CP_NOT_CONVERGED = 1, 2, 4, 8
+
+
+class LbmTuneReport(ctypes.Structure):
+    _fields_ = [("buckets", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("ms_before", ctypes.c_double),
+                ("ms_after", ctypes.c_double)]
 
 
 class LbmGeom(ctypes.Structure):
@@ -69,7 +76,7 @@ class LbmCpOptions(ctypes.Structure):
                 ("chunk_steps", ctypes.c_int32), ("still_chunks", ctypes.c_int32),
                 ("max_probes", ctypes.c_int32), ("verify_bracket", ctypes.c_int32),
                 ("min_steps", ctypes.c_int64), ("storage", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32)]
 
 
 class LbmCpResult(ctypes.Structure):
@@ -124,6 +131,9 @@ def load():
     lib.lbm_set_tiling.argtypes = [vp, i32, i32]
     lib.lbm_get_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
+    lib.lbm_set_instance_tiling.argtypes = [vp, i32, i32, i32]
+    lib.lbm_get_instance_tiling.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.lbm_autotune.argtypes = [vp, i32, ctypes.POINTER(LbmTuneReport)]
     lib.lbm_set_active.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
     lib.lbm_snapshot_save.argtypes = [vp]
     lib.lbm_snapshot_restore.argtypes = [vp, i32]

@@ -12,7 +12,8 @@ from . import _lib
 from ._lib import (CP_ADVANCE, CP_BEGIN, CP_MONITORS, GEOM_BOX, GEOM_CHANNEL, GEOM_MASK,
                    INIT_DROPLET, INIT_FIELD, INIT_LAYERS, INIT_SLUG, INIT_UNIFORM, OPT_SNAPSHOT,
                    STORE_BF16, STORE_F16, STORE_F32, LbmCpEngine, LbmCpOptions, LbmCpProblem,
-                   LbmCpResult, LbmFluid, LbmGeom, LbmInitFields, LbmMonitor, check)
+                   LbmCpResult, LbmFluid, LbmGeom, LbmInitFields, LbmMonitor, LbmTuneReport,
+                   check)
 
 _GEOM_KINDS = {"box": GEOM_BOX, "channel": GEOM_CHANNEL, "mask": GEOM_MASK}
 _INIT_KINDS = {"uniform": INIT_UNIFORM, "droplet": INIT_DROPLET, "layers": INIT_LAYERS,
@@ -171,6 +172,25 @@ def lbm_get_tiling(ctx):
     check(_lib.load().lbm_get_tiling(ctx, ctypes.byref(bx), ctypes.byref(st), ctypes.byref(n)),
           "lbm_get_tiling")
     return bx.value, st.value, n.value
+
+
+def lbm_set_instance_tiling(ctx, inst, bx, strip_rows):
+    check(_lib.load().lbm_set_instance_tiling(ctx, int(inst), int(bx), int(strip_rows)),
+          "lbm_set_instance_tiling")
+
+
+def lbm_get_instance_tiling(ctx, inst):
+    bx, st = ctypes.c_int32(), ctypes.c_int32()
+    check(_lib.load().lbm_get_instance_tiling(ctx, int(inst), ctypes.byref(bx), ctypes.byref(st)),
+          "lbm_get_instance_tiling")
+    return bx.value, st.value
+
+
+def lbm_autotune(ctx, steps_per_trial=32):
+    r = LbmTuneReport()
+    check(_lib.load().lbm_autotune(ctx, int(steps_per_trial), ctypes.byref(r)), "lbm_autotune")
+    return {"buckets": r.buckets, "trials": r.trials, "steps": r.steps,
+            "ms_before": r.ms_before, "ms_after": r.ms_after}
 
 
 def lbm_set_active(ctx, active):
@@ -361,6 +381,16 @@ class Simulation:
 
     def tiling(self):
         return lbm_get_tiling(self.ctx)
+
+    def set_instance_tiling(self, inst, bx, strip_rows):
+        lbm_set_instance_tiling(self.ctx, inst, bx, strip_rows)
+
+    def instance_tiling(self, inst):
+        return lbm_get_instance_tiling(self.ctx, inst)
+
+    def autotune(self, steps_per_trial=32):
+        """Tune the tiling per width class; advances the run by the steps timed."""
+        return lbm_autotune(self.ctx, steps_per_trial)
 
     def fluid_mask(self, inst=0):
         c = self.configs[inst]

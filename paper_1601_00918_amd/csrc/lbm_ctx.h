@@ -45,6 +45,7 @@ struct lbm_ctx {
     std::vector<InstHost> ih;
     std::vector<InstDev> idv;
     std::vector<Item> items;
+    std::vector<Item> act_items;  // items of the active instances (host copy)
     std::vector<int32_t> item_first, item_count;
     Layout L{};
     char* ws = nullptr;
@@ -62,8 +63,15 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     int cur = 0;
     int64_t t = 0;
-    int bx = 256;
+    // Tiling: per instance, columns per workgroup (64, 128, 256) and rows per
+    // strip.  Items are grouped by workgroup width (one launch per width and
+    // step): cls_first / cls_count index the full item list, act_first /
+    // act_count the active list, in the order of kBxClasses.
+    int bx = 256;    // last value set for every instance
     int strip = 8;
+    std::vector<int> ibx, istrip;
+    int cls_first[3] = {0, 0, 0}, cls_count[3] = {0, 0, 0};
+    int act_first[3] = {0, 0, 0}, act_count[3] = {0, 0, 0};
     // Work items being stepped: a copy of the items of the active instances,
     // stored on the device after the full list (at items_d + L.n_items_max).
     std::vector<uint8_t> active;

@@ -338,9 +338,32 @@ lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
         return e;
     eng.fluids = fluids;
     eng.cur_active.assign(n, 1);
-    // Unforced equilibration, each problem for its own number of steps.
+    // Unforced equilibration, each problem for its own number of steps; the
+    // autotuner's timed steps are its first steps when every problem has room.
     std::vector<int64_t> steps0(n, 0);
     int64_t done = 0;
+    if (o.autotune) {
+        constexpr int kTrial = 32;
+        std::vector<int> widths;
+        int64_t min_equil = probs[0].equil_steps;
+        for (int k = 0; k < n; ++k) {
+            min_equil = std::min(min_equil, probs[k].equil_steps);
+            if (std::find(widths.begin(), widths.end(), probs[k].geom.nx) == widths.end())
+                widths.push_back(probs[k].geom.nx);
+        }
+        // at most 3 + 11 trials per width class (lbm_autotune)
+        const int64_t bound = (int64_t)kTrial * (3 + 11 * (int64_t)widths.size());
+        if (min_equil >= bound) {
+            lbm_tune_report rep{};
+            if ((e = lbm_autotune(eng.ctx, kTrial, &rep)) != LBM_OK) {
+                lbm_destroy(eng.ctx);
+                return e;
+            }
+            done = rep.steps;
+            for (int k = 0; k < n; ++k)
+                steps0[k] = rep.steps;
+        }
+    }
     for (;;) {
         std::vector<uint8_t> act(n, 0);
         int64_t next = -1;

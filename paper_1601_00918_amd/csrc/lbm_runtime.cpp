@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -231,57 +232,73 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
     d.Gd = f.G;
 }
 
+constexpr int kBxClasses[3] = {256, 128, 64};
+
+int bx_class(int bx) { return bx == 256 ? 0 : (bx == 128 ? 1 : 2); }
+
 // Cut every instance into work items: blocks of bx columns, each split into
-// strips of `strip` rows covering the block's fluid rows.  Items are ordered
-// strip-major (all column blocks of one band of rows, then the next band), so
-// the blocks that share boundary cache lines run side by side on one XCD.
+// strips of `strip` rows covering the block's fluid rows.  An instance's items
+// are ordered strip-major (all column blocks of one band of rows, then the
+// next band), so the blocks that share boundary cache lines run side by side
+// on one XCD.  Instances are grouped by their workgroup width.
 void build_items(lbm_ctx* c)
 {
     c->items.clear();
     c->item_first.assign(c->n_inst, 0);
     c->item_count.assign(c->n_inst, 0);
-    for (int k = 0; k < c->n_inst; ++k) {
-        const InstHost& h = c->ih[k];
-        c->item_first[k] = (int32_t)c->items.size();
-        const int nblk = (h.nx + c->bx - 1) / c->bx;
-        std::vector<int> ylo(nblk, h.ny), yhi(nblk, -1);
-        int glo = h.ny, ghi = -1;
-        for (int b = 0; b < nblk; ++b) {
-            for (int x = b * c->bx; x < std::min(h.nx, (b + 1) * c->bx); ++x)
-                if (h.cols[x].lo <= h.cols[x].hi) {
-                    ylo[b] = std::min(ylo[b], h.cols[x].lo);
-                    yhi[b] = std::max(yhi[b], h.cols[x].hi);
-                }
-            glo = std::min(glo, ylo[b]);
-            ghi = std::max(ghi, yhi[b]);
-        }
-        int band = 0;
-        for (int y0 = glo; y0 <= ghi; y0 += c->strip, ++band) {
-            const int y1 = std::min(ghi + 1, y0 + c->strip);
+    for (int cl = 0; cl < 3; ++cl) {
+        c->cls_first[cl] = (int)c->items.size();
+        for (int k = 0; k < c->n_inst; ++k) {
+            const int bx = c->ibx[k], strip = c->istrip[k];
+            if (bx != kBxClasses[cl])
+                continue;
+            const InstHost& h = c->ih[k];
+            c->item_first[k] = (int32_t)c->items.size();
+            const int nblk = (h.nx + bx - 1) / bx;
+            std::vector<int> ylo(nblk, h.ny), yhi(nblk, -1);
+            int glo = h.ny, ghi = -1;
             for (int b = 0; b < nblk; ++b) {
-                const int a0 = std::max(y0, ylo[b]), a1 = std::min(y1, yhi[b] + 1);
-                if (a0 >= a1)
-                    continue;
-                // odd bands march down: rows a1 - 1 .. a0
-                if (band & 1)
-                    c->items.push_back(Item{k, b * c->bx, a1 - 1, a0 - 1});
-                else
-                    c->items.push_back(Item{k, b * c->bx, a0, a1});
+                for (int x = b * bx; x < std::min(h.nx, (b + 1) * bx); ++x)
+                    if (h.cols[x].lo <= h.cols[x].hi) {
+                        ylo[b] = std::min(ylo[b], h.cols[x].lo);
+                        yhi[b] = std::max(yhi[b], h.cols[x].hi);
+                    }
+                glo = std::min(glo, ylo[b]);
+                ghi = std::max(ghi, yhi[b]);
             }
+            int band = 0;
+            for (int y0 = glo; y0 <= ghi; y0 += strip, ++band) {
+                const int y1 = std::min(ghi + 1, y0 + strip);
+                for (int b = 0; b < nblk; ++b) {
+                    const int a0 = std::max(y0, ylo[b]), a1 = std::min(y1, yhi[b] + 1);
+                    if (a0 >= a1)
+                        continue;
+                    // odd bands march down: rows a1 - 1 .. a0
+                    if (band & 1)
+                        c->items.push_back(Item{k, b * bx, a1 - 1, a0 - 1});
+                    else
+                        c->items.push_back(Item{k, b * bx, a0, a1});
+                }
+            }
+            c->item_count[k] = (int32_t)c->items.size() - c->item_first[k];
         }
-        c->item_count[k] = (int32_t)c->items.size() - c->item_first[k];
+        c->cls_count[cl] = (int)c->items.size() - c->cls_first[cl];
     }
 }
 
-// Items of the active instances, in instance order.
-std::vector<Item> active_items(const lbm_ctx* c)
+// Items of the active instances, grouped like the full list.
+std::vector<Item> active_items(lbm_ctx* c)
 {
     std::vector<Item> v;
     v.reserve(c->items.size());
-    for (int k = 0; k < c->n_inst; ++k)
-        if (c->active[k])
-            v.insert(v.end(), c->items.begin() + c->item_first[k],
-                     c->items.begin() + c->item_first[k] + c->item_count[k]);
+    for (int cl = 0; cl < 3; ++cl) {
+        c->act_first[cl] = (int)v.size();
+        for (int k = 0; k < c->n_inst; ++k)
+            if (c->active[k] && c->ibx[k] == kBxClasses[cl])
+                v.insert(v.end(), c->items.begin() + c->item_first[k],
+                         c->items.begin() + c->item_first[k] + c->item_count[k]);
+        c->act_count[cl] = (int)v.size() - c->act_first[cl];
+    }
     return v;
 }
 
@@ -289,7 +306,8 @@ lbm_status upload_tables(lbm_ctx* c)
 {
     HIP_TRY(hipMemcpyAsync(c->items_d, c->items.data(), sizeof(Item) * c->items.size(),
                            hipMemcpyHostToDevice, c->stream));
-    const std::vector<Item> act = active_items(c);
+    c->act_items = active_items(c);  // kept: the source of an asynchronous copy
+    const std::vector<Item>& act = c->act_items;
     c->n_active_items = (int)act.size();
     if (!act.empty())
         HIP_TRY(hipMemcpyAsync(c->items_d + c->L.n_items_max, act.data(), sizeof(Item) * act.size(),
@@ -326,14 +344,32 @@ lbm_status sync_all(lbm_ctx* c)
     return LBM_OK;
 }
 
-lbm_status run_mode(lbm_ctx* c, int mode, int item_base, int n_items, uint32_t seed = 0,
-                    const uint32_t* seed_dev = nullptr)
+lbm_status run_range(lbm_ctx* c, int bx, int mode, int item_base, int n_items,
+                     uint32_t seed = 0, const uint32_t* seed_dev = nullptr)
 {
-    hipError_t e = launch_step(c->storage, c->bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1],
+    hipError_t e = launch_step(c->storage, bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1],
                                c->inst_d, c->items_d, item_base, n_items, c->cols_d,
                                c->partial_d, c->stage_d, seed, seed_dev, c->stream);
     if (e != hipSuccess)
         return fail(LBM_ERR_DEVICE, "step launch failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// One pass of `mode` over the active items (kStep, kStepMon) or over every
+// item (kMonOnly): one launch per workgroup width.
+lbm_status run_mode(lbm_ctx* c, int mode, uint32_t seed = 0, const uint32_t* seed_dev = nullptr)
+{
+    const bool act = mode == kStep || mode == kStepMon;
+    const int base = act ? (int)c->L.n_items_max : 0;
+    for (int cl = 0; cl < 3; ++cl) {
+        const int first = act ? c->act_first[cl] : c->cls_first[cl];
+        const int n = act ? c->act_count[cl] : c->cls_count[cl];
+        if (n == 0)
+            continue;
+        lbm_status st = run_range(c, kBxClasses[cl], mode, base + first, n, seed, seed_dev);
+        if (st != LBM_OK)
+            return st;
+    }
     return LBM_OK;
 }
 
@@ -463,6 +499,8 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     // rows and block-boundary lines are shared in L2).
     c->bx = max_nx >= 256 ? 256 : (max_nx >= 128 ? 128 : 64);
     c->strip = 8;
+    c->ibx.assign(n_inst, c->bx);
+    c->istrip.assign(n_inst, c->strip);
     build_items(c);
 
     lbm_status st = LBM_OK;
@@ -525,8 +563,7 @@ static lbm_status step_direct(lbm_ctx* c, int64_t nsteps, bool in_graph = false)
 {
     for (int64_t k = 0; k < nsteps; ++k) {
         const uint32_t seed = in_graph ? (uint32_t)k : (uint32_t)c->t;
-        lbm_status st = run_mode(c, kStep, (int)c->L.n_items_max, c->n_active_items, seed,
-                                 in_graph ? c->seed_d : nullptr);
+        lbm_status st = run_mode(c, kStep, seed, in_graph ? c->seed_d : nullptr);
         if (st != LBM_OK)
             return st;
         c->cur ^= 1;
@@ -669,7 +706,7 @@ lbm_status lbm_monitors(lbm_ctx* c, lbm_monitor* mon)
     lbm_status st = sync_all(c);
     if (st != LBM_OK)
         return st;
-    st = run_mode(c, kMonOnly, 0, (int)c->items.size());
+    st = run_mode(c, kMonOnly);
     if (st != LBM_OK)
         return st;
     hipError_t e = launch_mon_reduce(c->partial_d, c->first_d, c->count_d, c->n_inst, c->mon_d,
@@ -691,7 +728,7 @@ static lbm_status export_instance(lbm_ctx* c, int inst)
     const InstHost& h = c->ih[inst];
     const size_t n = (size_t)h.nx * h.ny;
     HIP_TRY(hipMemsetAsync(c->stage_d, 0, sizeof(double) * kExportFields * n, c->stream));
-    return run_mode(c, kExport, c->item_first[inst], c->item_count[inst]);
+    return run_range(c, c->ibx[inst], kExport, c->item_first[inst], c->item_count[inst]);
 }
 
 lbm_status lbm_moments(lbm_ctx* c, int32_t inst, double* rho, double* u, double* p,
@@ -763,8 +800,38 @@ lbm_status lbm_set_tiling(lbm_ctx* c, int32_t bx, int32_t strip_rows)
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->bx = bx;
     c->strip = strip_rows;
+    c->ibx.assign(c->n_inst, bx);
+    c->istrip.assign(c->n_inst, strip_rows);
     build_items(c);
     return upload_tables(c);
+}
+
+lbm_status lbm_set_instance_tiling(lbm_ctx* c, int32_t inst, int32_t bx, int32_t strip_rows)
+{
+    if (!c || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_set_instance_tiling: null context or bad instance");
+    if (bx != 64 && bx != 128 && bx != 256)
+        return fail(LBM_ERR_INVALID, "lbm_set_instance_tiling: bx must be 64, 128 or 256");
+    if (strip_rows < kMinStrip || strip_rows > 32768)
+        return fail(LBM_ERR_INVALID, "lbm_set_instance_tiling: strip_rows must be >= %d",
+                    kMinStrip);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->ibx[inst] = bx;
+    c->istrip[inst] = strip_rows;
+    build_items(c);
+    return upload_tables(c);
+}
+
+lbm_status lbm_get_instance_tiling(const lbm_ctx* c, int32_t inst, int32_t* bx,
+                                   int32_t* strip_rows)
+{
+    if (!c || inst < 0 || inst >= c->n_inst)
+        return fail(LBM_ERR_INVALID, "lbm_get_instance_tiling: null context or bad instance");
+    if (bx)
+        *bx = c->ibx[inst];
+    if (strip_rows)
+        *strip_rows = c->istrip[inst];
+    return LBM_OK;
 }
 
 lbm_status lbm_get_tiling(const lbm_ctx* c, int32_t* bx, int32_t* strip_rows, int32_t* n_items)
@@ -777,6 +844,108 @@ lbm_status lbm_get_tiling(const lbm_ctx* c, int32_t* bx, int32_t* strip_rows, in
         *strip_rows = c->strip;
     if (n_items)
         *n_items = (int32_t)c->items.size();
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial, lbm_tune_report* report)
+{
+    if (!c || steps_per_trial < 2)
+        return fail(LBM_ERR_INVALID, "lbm_autotune: null context or steps_per_trial < 2");
+    if (c->n_active_items == 0)
+        return fail(LBM_ERR_INVALID, "lbm_autotune: no active instance");
+    // Buckets: active instances of equal width, largest total fluid nodes first.
+    std::vector<std::pair<int64_t, int>> order;  // (fluid nodes, nx)
+    for (int k = 0; k < c->n_inst; ++k) {
+        if (!c->active[k])
+            continue;
+        int64_t nodes = 0;
+        for (const Col& cc : c->ih[k].cols)
+            nodes += std::max(0, cc.hi - cc.lo + 1);
+        auto it = std::find_if(order.begin(), order.end(),
+                               [&](const std::pair<int64_t, int>& b) { return b.second == c->ih[k].nx; });
+        if (it == order.end())
+            order.emplace_back(nodes, c->ih[k].nx);
+        else
+            it->first += nodes;
+    }
+    std::sort(order.begin(), order.end(), std::greater<std::pair<int64_t, int>>());
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LBM_ERR_DEVICE, "lbm_autotune: hipEventCreate failed");
+    }
+    lbm_tune_report rep{};
+    lbm_status st = LBM_OK;
+    // Per-step time of steps_per_trial real steps with the current tiling.
+    auto trial = [&](double& ms) -> lbm_status {
+        if (hipEventRecord(e0, c->stream) != hipSuccess)
+            return fail(LBM_ERR_DEVICE, "lbm_autotune: event record failed");
+        lbm_status s2 = lbm_step(c, steps_per_trial);
+        if (s2 != LBM_OK)
+            return s2;
+        float t = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return fail(LBM_ERR_DEVICE, "lbm_autotune: event timing failed");
+        ms = (double)t / steps_per_trial;
+        ++rep.trials;
+        rep.steps += steps_per_trial;
+        return LBM_OK;
+    };
+    auto apply = [&](int nx, int bx, int strip) -> lbm_status {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int k = 0; k < c->n_inst; ++k)
+            if (c->active[k] && c->ih[k].nx == nx) {
+                c->ibx[k] = bx;
+                c->istrip[k] = strip;
+            }
+        build_items(c);
+        return upload_tables(c);
+    };
+    double best = 0.0, ms = 0.0;
+    static const int kStrips[] = {4, 8, 16, 32};
+    if ((st = trial(ms)) == LBM_OK)  // warm-up (graph capture, caches)
+        st = trial(best);
+    rep.ms_before = best;
+    for (size_t b = 0; st == LBM_OK && b < order.size(); ++b) {
+        const int nx = order[b].second;
+        int kb = -1;
+        for (int k = 0; k < c->n_inst; ++k)
+            if (c->active[k] && c->ih[k].nx == nx) {
+                kb = k;
+                break;
+            }
+        int cur_bx = c->ibx[kb], cur_strip = c->istrip[kb];
+        for (int cl = 0; st == LBM_OK && cl < 3; ++cl) {
+            const int bx = kBxClasses[cl];
+            if (bx > 64 && bx > (int)align_up((size_t)nx, 64))
+                continue;
+            for (int strip : kStrips) {
+                if (bx == cur_bx && strip == cur_strip)
+                    continue;
+                if ((st = apply(nx, bx, strip)) != LBM_OK || (st = trial(ms)) != LBM_OK)
+                    break;
+                if (ms < best * 0.997) {
+                    best = ms;
+                    cur_bx = bx;
+                    cur_strip = strip;
+                }
+            }
+        }
+        if (st == LBM_OK)
+            st = apply(nx, cur_bx, cur_strip);
+    }
+    if (st == LBM_OK)
+        st = trial(rep.ms_after);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBM_OK)
+        return st;
+    rep.buckets = (int32_t)order.size();
+    if (report)
+        *report = rep;
     return LBM_OK;
 }
 
