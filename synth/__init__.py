@@ -202,3 +202,26 @@ def rho0_of(cfg, mask=None):
     if ini["kind"] == "slug":
         return slug_field(nx, ny, ini["x0"], ini["length"], mask)
     raise ValueError(ini["kind"])
+
+
+def mlp_init(seed=918, sizes=(6, 128, 128, 128, 1)):
+    """Initial parameters of the surrogate network as one flat float32 vector
+    (layout W1, b1, W2, b2, W3, b3, W4, b4, weights one row per output unit):
+    weights uniform in +-1/sqrt(fan_in), biases zero, from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        k, n = sizes[i], sizes[i + 1]
+        bound = 1.0 / math.sqrt(k)
+        parts.append(rng.uniform(-bound, bound, size=n * k))
+        parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(n, seed=7, sizes=(6, 128, 128, 128, 1)):
+    """Random standardised inputs [n, 6] and targets [n] (float32) for the
+    network's parity tests."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, sizes[0])).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    return X, t
