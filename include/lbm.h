@@ -292,9 +292,15 @@ typedef struct {
     int32_t chunk_steps;    /* steps between monitor checks, default 1000 (even) */
     int32_t still_chunks;   /* default 3 */
     int32_t max_probes;     /* default 60 */
-    int32_t verify_bracket; /* 1: probe both ends first and widen the bracket
-                               (by a factor 10^0.5 per try) until g_lo is static and
-                               g_hi is moving */
+    int32_t verify_bracket; /* 0 (default): trust [g_lo, g_hi].
+                               1: probe both ends first and widen the bracket (by a
+                               factor 10^0.5 per try) until g_lo is static and g_hi
+                               is moving, then bisect.
+                               2 (lazy, for predicted brackets): bisect first; once
+                               the bracket is within rel_tol, probe each end that was
+                               never probed; an end that fails moves the bracket out
+                               by 10^0.5 and bisection resumes.  At most 8 widenings
+                               (then LBM_CP_NOT_CONVERGED). */
     int64_t min_steps;      /* default 20000 */
     int32_t storage;        /* lbm_storage of the populations, default LBM_STORE_F32 */
     int32_t autotune;       /* 1: run lbm_autotune (32 steps per trial) at the start of

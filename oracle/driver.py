@@ -10,6 +10,12 @@ for still_chunks consecutive checks and the slug has advanced less than
 creep_frac * lambda, U_ref = g h0^2 / (3 nu_w); at the step budget, moving iff it
 advanced creep_frac * lambda; a non-physical state counts as moving; stop when
 (g_hi - g_lo) / g_lo <= rel_tol).  It shares no code with the library.
+
+Bracket checks (verify_bracket): 0 trusts the given bracket; 1 probes g_lo
+and then g_hi before bisecting, widening by sqrt(10) past an end that fails;
+2 ("lazy") bisects first and probes an end of the given bracket only if the
+converged bracket still has it as an end (it was never probed), widening by
+sqrt(10) and bisecting on when it fails.
 """
 import math
 
@@ -47,9 +53,11 @@ def solve(engine, problems, **rules):
     x_start = [_centre(mon[k], problems[k]["nx"]) for k in range(n)]
     st = []
     for k, p in enumerate(problems):
+        eager = R["verify_bracket"] == 1
         s = dict(lo=p["g_lo"], hi=p["g_hi"], widen=0, probes=0, flags=0, history=[],
-                 phase="verify_lo" if R["verify_bracket"] else "bisect")
-        s["g"] = s["lo"] if R["verify_bracket"] else math.sqrt(s["lo"] * s["hi"])
+                 phase="verify_lo" if eager else "bisect",
+                 lo_ok=R["verify_bracket"] != 2, hi_ok=R["verify_bracket"] != 2)
+        s["g"] = s["lo"] if eager else math.sqrt(s["lo"] * s["hi"])
         st.append(s)
 
     def begin(k):
@@ -117,13 +125,42 @@ def solve(engine, problems, **rules):
                 else:
                     s["phase"] = "bisect"
                     s["g"] = math.sqrt(s["lo"] * s["hi"])
+            elif s["phase"] == "check_lo":
+                if not moving:
+                    s["lo_ok"] = True
+                elif s["widen"] < 8:
+                    s["widen"] += 1
+                    s["flags"] |= WIDENED
+                    s["hi"], s["hi_ok"] = s["lo"], True
+                    s["lo"] /= math.sqrt(10.0)
+                else:
+                    s["flags"] |= NOT_CONVERGED
+                    s["phase"] = "done"
+            elif s["phase"] == "check_hi":
+                if moving:
+                    s["hi_ok"] = True
+                elif s["widen"] < 8:
+                    s["widen"] += 1
+                    s["flags"] |= WIDENED
+                    s["lo"], s["lo_ok"] = s["hi"], True
+                    s["hi"] *= math.sqrt(10.0)
+                else:
+                    s["flags"] |= NOT_CONVERGED
+                    s["phase"] = "done"
             else:
                 if moving:
-                    s["hi"] = s["g"]
+                    s["hi"], s["hi_ok"] = s["g"], True
                 else:
-                    s["lo"] = s["g"]
-                s["g"] = math.sqrt(s["lo"] * s["hi"])
-                if (s["hi"] - s["lo"]) / s["lo"] <= R["rel_tol"]:
+                    s["lo"], s["lo_ok"] = s["g"], True
+            if s["phase"] in ("bisect", "check_lo", "check_hi"):
+                # next probe: bisect while wide, then the unprobed ends
+                if (s["hi"] - s["lo"]) / s["lo"] > R["rel_tol"]:
+                    s["phase"], s["g"] = "bisect", math.sqrt(s["lo"] * s["hi"])
+                elif not s["lo_ok"]:
+                    s["phase"], s["g"] = "check_lo", s["lo"]
+                elif not s["hi_ok"]:
+                    s["phase"], s["g"] = "check_hi", s["hi"]
+                else:
                     s["phase"] = "done"
             if s["phase"] != "done" and s["probes"] >= R["max_probes"]:
                 s["flags"] |= NOT_CONVERGED

@@ -25,6 +25,7 @@ EXPORTED = [
     "lbm_snapshot_save", "lbm_snapshot_restore", "lbm_cp_default_options",
     "lbm_cp_required_bytes", "lbm_critical_pressure", "lbm_cp_drive",
     "lbm_set_instance_tiling", "lbm_get_instance_tiling", "lbm_autotune",
+    "lbm_mlp_workspace_bytes", "lbm_mlp_forward", "lbm_mlp_backward", "lbm_mlp_adam",
 ]
 
 OPT_SNAPSHOT = 0x100
@@ -147,9 +148,15 @@ def load():
                                  ctypes.POINTER(LbmCpOptions), ctypes.POINTER(LbmCpResult)]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
+    lib.lbm_mlp_workspace_bytes.argtypes = [i32]
+    lib.lbm_mlp_workspace_bytes.restype = sz
+    lib.lbm_mlp_forward.argtypes = [vp, vp, i32, vp, vp, sz, vp]
+    lib.lbm_mlp_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
+    fl = ctypes.c_float
+    lib.lbm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy",
-                        "lbm_cp_default_options"):
+                        "lbm_cp_default_options", "lbm_mlp_workspace_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib

@@ -28,11 +28,12 @@ struct CpEngine {
 };
 
 enum Outcome { kNone, kStatic, kMoving };
-enum Phase { kVerifyLo, kVerifyHi, kBisect, kDone };
+enum Phase { kVerifyLo, kVerifyHi, kBisect, kCheckLo, kCheckHi, kDone };
 
 struct ProbeState {
     Phase phase = kBisect;
     double g_lo = 0, g_hi = 0, g = 0;
+    bool lo_ok = true, hi_ok = true;  // the end has been probed (or is trusted)
     int widen = 0;
     // current probe
     int64_t probe_steps = 0;
@@ -73,7 +74,8 @@ lbm_status check_options(const lbm_cp_options& o)
 {
     if (!(o.rel_tol > 0.0) || !(o.move_frac > 0.0) || !(o.creep_frac > 0.0) ||
         !(o.still_frac > 0.0) || o.chunk_steps < 2 || (o.chunk_steps & 1) || o.still_chunks < 1 ||
-        o.max_probes < 1 || o.min_steps < 0 || o.storage < LBM_STORE_F32 ||
+        o.max_probes < 1 || o.min_steps < 0 || o.verify_bracket < 0 || o.verify_bracket > 2 ||
+        o.storage < LBM_STORE_F32 ||
         o.storage > LBM_STORE_BF16)
         return fail(LBM_ERR_INVALID, "invalid critical-pressure options");
     return LBM_OK;
@@ -125,8 +127,10 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
         ProbeState& s = st[k];
         s.g_lo = p.g_lo;
         s.g_hi = p.g_hi;
-        s.phase = o.verify_bracket ? kVerifyLo : kBisect;
-        s.g = o.verify_bracket ? s.g_lo : std::sqrt(s.g_lo * s.g_hi);
+        const bool eager = o.verify_bracket == 1;
+        s.phase = eager ? kVerifyLo : kBisect;
+        s.g = eager ? s.g_lo : std::sqrt(s.g_lo * s.g_hi);
+        s.lo_ok = s.hi_ok = o.verify_bracket != 2;
         std::memset(&res[k], 0, sizeof(lbm_cp_result));
         res[k].steps = steps0[k];
     }
@@ -187,15 +191,58 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
                     s.g = std::sqrt(s.g_lo * s.g_hi);
                 }
                 break;
-            default:
-                if (moving)
-                    s.g_hi = s.g;
-                else
-                    s.g_lo = s.g;
-                s.g = std::sqrt(s.g_lo * s.g_hi);
-                if ((s.g_hi - s.g_lo) / s.g_lo <= o.rel_tol)
+            case kCheckLo:
+                if (!moving) {
+                    s.lo_ok = true;
+                } else if (s.widen < kMaxWiden) {
+                    ++s.widen;
+                    r.flags |= LBM_CP_WIDENED;
+                    s.g_hi = s.g_lo;
+                    s.hi_ok = true;
+                    s.g_lo /= std::sqrt(10.0);
+                } else {
+                    r.flags |= LBM_CP_NOT_CONVERGED;
                     s.phase = kDone;
+                }
                 break;
+            case kCheckHi:
+                if (moving) {
+                    s.hi_ok = true;
+                } else if (s.widen < kMaxWiden) {
+                    ++s.widen;
+                    r.flags |= LBM_CP_WIDENED;
+                    s.g_lo = s.g_hi;
+                    s.lo_ok = true;
+                    s.g_hi *= std::sqrt(10.0);
+                } else {
+                    r.flags |= LBM_CP_NOT_CONVERGED;
+                    s.phase = kDone;
+                }
+                break;
+            default:
+                if (moving) {
+                    s.g_hi = s.g;
+                    s.hi_ok = true;
+                } else {
+                    s.g_lo = s.g;
+                    s.lo_ok = true;
+                }
+                break;
+            }
+            if (s.phase == kBisect || s.phase == kCheckLo || s.phase == kCheckHi) {
+                // next probe: bisect while wide, then the ends never probed
+                if ((s.g_hi - s.g_lo) / s.g_lo > o.rel_tol) {
+                    s.phase = kBisect;
+                    s.g = std::sqrt(s.g_lo * s.g_hi);
+                } else if (!s.lo_ok) {
+                    s.phase = kCheckLo;
+                    s.g = s.g_lo;
+                } else if (!s.hi_ok) {
+                    s.phase = kCheckHi;
+                    s.g = s.g_hi;
+                } else {
+                    s.phase = kDone;
+                }
             }
             if (s.phase != kDone && r.probes >= o.max_probes) {
                 r.flags |= LBM_CP_NOT_CONVERGED;

@@ -234,8 +234,6 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
 
 constexpr int kBxClasses[3] = {256, 128, 64};
 
-int bx_class(int bx) { return bx == 256 ? 0 : (bx == 128 ? 1 : 2); }
-
 // Cut every instance into work items: blocks of bx columns, each split into
 // strips of `strip` rows covering the block's fluid rows.  An instance's items
 // are ordered strip-major (all column blocks of one band of rows, then the

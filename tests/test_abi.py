@@ -1,4 +1,4 @@
-"""The C-ABI library loads, exports every entry point include/lbm.h declares,
+"""The C-ABI library loads, exports every entry point include/*.h declares,
 and its host-side validation works (no GPU needed: nothing here launches a
 kernel or touches device memory)."""
 import ctypes
@@ -14,9 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names.update(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_list():
@@ -89,3 +93,13 @@ def test_mask_with_two_fluid_runs_in_a_column_is_unsupported():
     with pytest.raises(_lib.LbmError) as e:
         _try_init([g], [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct("uniform")])
     assert e.value.status == 6 and "column 3" in str(e.value)
+
+
+def test_mlp_entry_points_validate_on_the_host():
+    lib = _lib.load()
+    assert lib.lbm_mlp_workspace_bytes(0) == 0
+    # nine [B_padded x 128] planes plus one loss partial per 16 samples
+    assert lib.lbm_mlp_workspace_bytes(20) == 4 * (9 * 32 * 128 + 2)
+    null = ctypes.c_void_p(0)
+    assert lib.lbm_mlp_forward(null, null, 4, null, null, 0, null) == 1
+    assert lib.lbm_mlp_adam(null, null, null, null, 0, 1e-3, 0.9, 0.999, 1e-8, null) == 1

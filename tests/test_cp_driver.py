@@ -136,3 +136,34 @@ def test_driver_rejects_bad_problems():
     probs[0].g_lo = 0.0
     with pytest.raises(binding._lib.LbmError):
         binding.lbm_cp_drive(FakeEngine(plain, [1e-5]), probs, binding.cp_options())
+
+
+def test_lazy_bracket_check_matches_the_oracle_and_recovers_wrong_brackets():
+    """verify_bracket = 2: a bracket around the threshold costs no end probes;
+    a bracket that misses it is widened after convergence; both drivers
+    probe the same g sequence."""
+    g_stars = [5e-5, 5e-5, 5e-5, 5e-5]
+    probs, plain = _problems(g_stars, span=1.0)
+    brackets = [(4e-5, 6e-5), (2e-4, 4e-4), (1e-6, 2e-6), (4.99e-5, 5.2e-5)]
+    for p, q, (lo, hi) in zip(probs, plain, brackets):
+        p.g_lo, p.g_hi = lo, hi
+        q.update(g_lo=lo, g_hi=hi)
+    history = [[] for _ in g_stars]
+
+    class Recording(FakeEngine):
+        def begin_probe(self, k, g):
+            history[k].append(g)
+            super().begin_probe(k, g)
+
+    opts = binding.cp_options(verify_bracket=2)
+    lib = binding.lbm_cp_drive(Recording(plain, g_stars), probs, opts)
+    ref = odrv.solve(FakeEngine(plain, g_stars), plain, verify_bracket=2)
+    for k, (r, o) in enumerate(zip(lib, ref)):
+        assert len(history[k]) == len(o["history"])
+        for a, b in zip(history[k], o["history"]):
+            assert a == pytest.approx(b, rel=1e-12)
+        assert r["g_crit"] == pytest.approx(o["g_crit"], rel=1e-12) and r["flags"] == o["flags"]
+        assert r["g_lo"] <= 5e-5 <= r["g_hi"] and (r["g_hi"] - r["g_lo"]) / r["g_lo"] <= 0.005
+    # inside bracket: plain bisection, no end probes, no widening
+    assert lib[0]["flags"] == 0 and lib[0]["probes"] == math.ceil(math.log2(math.log(1.5) / 0.005))
+    assert lib[1]["flags"] & binding._lib.CP_WIDENED and lib[2]["flags"] & binding._lib.CP_WIDENED
