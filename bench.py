@@ -119,6 +119,94 @@ def copy_calibration(steps, warmup, nbytes=2 << 30):
                       "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}), flush=True)
 
 
+def solves_per_hour(args):
+    """Critical-pressure solves per hour: plain single-instance bisection vs
+    batched solves with surrogate brackets, on channels of the batch family
+    with lambda ~ U{64, 128} (theta ~ U(30, 150) deg, viscosity ratio
+    ~ logU(0.1, 10)).  The surrogate is trained first on batched plain solves
+    of other channels of the same family; its cost is reported apart."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1601_00918_amd import _lib
+    from paper_1601_00918_amd import surrogate as sg
+
+    SIG, RHO = 0.161, 1.03
+    rules = dict(rel_tol=0.005, chunk_steps=500, still_chunks=3)
+    lams = (64, 128)
+    n_eval = args.solves
+    train = synth.config_cp_set(n_eval, seed=1611, lams=lams)
+    evals = synth.config_cp_set(n_eval, seed=1612, lams=lams)
+    stream = torch.cuda.Stream()
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def log(msg):
+        print("solves: " + msg, file=sys.stderr, flush=True)
+
+    # 1. training data: batched plain solves of the training channels
+    tr, t_data = timed(lambda: sg.solve(train, [sg.plain_bracket(c, SIG, RHO) for c in train],
+                                        SIG, RHO, stream=stream, autotune=1, **rules))
+    ok = [i for i, r in enumerate(tr) if r["flags"] & ~_lib.CP_UNDECIDED == 0]
+    F = np.stack([sg.features(train[i]) for i in ok])
+    y = np.log10([tr[i]["bo_crit"] for i in ok])
+    sur, t_fit = timed(lambda: sg.Surrogate(synth.mlp_init(918)).fit(
+        F, y, np.random.default_rng(0), epochs=600))
+    log("training data %d solves in %.1f s, fit %.1f s, validation rmse %.4f" % (
+        len(train), t_data, t_fit, sur.sigma_val))
+    # 2. batched + surrogate on the evaluation channels (inference included)
+    def batched_sur():
+        br = sur.brackets(evals, SIG, RHO, k=2.0)
+        return sg.solve(evals, br, SIG, RHO, stream=stream, verify_bracket=2, autotune=1,
+                        **rules)
+    bs, t_bs = timed(batched_sur)
+    # 3. batched plain (no surrogate), for the split of the gain
+    bp, t_bp = timed(lambda: sg.solve(evals, [sg.plain_bracket(c, SIG, RHO) for c in evals],
+                                      SIG, RHO, stream=stream, autotune=1, **rules))
+    log("batched: surrogate %.1f s, plain %.1f s for %d solves" % (t_bs, t_bp, n_eval))
+    # 4. plain single-instance solves: a stratified subset, two per lambda
+    subset = []
+    for lam in lams:
+        subset += [i for i, c in enumerate(evals) if c["lam"] == lam][:2]
+    per_lam = {lam: [] for lam in lams}
+    single = {}
+    for i in subset:
+        c = evals[i]
+        r, dt = timed(lambda: sg.solve([c], [sg.plain_bracket(c, SIG, RHO)], SIG, RHO,
+                                       stream=stream, **rules)[0])
+        single[i] = r
+        per_lam[c["lam"]].append(dt)
+        log("single lambda %d: %.1f s, %d probes" % (c["lam"], dt, r["probes"]))
+    mix = {lam: sum(1 for c in evals if c["lam"] == lam) / n_eval for lam in lams}
+    t_single = sum(mix[lam] * float(np.mean(per_lam[lam])) for lam in lams)
+    agree = max(abs(bs[i]["g_crit"] / single[i]["g_crit"] - 1) for i in subset)
+    plain_rate = 3600.0 / t_single
+    rate = 3600.0 * n_eval / t_bs
+    return {
+        "metric": "critical-pressure solves/hr, batched + surrogate vs plain single-instance",
+        "value": round(rate, 1), "unit": "solves/hr", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "channels of the batch family, lambda ~ U{64,128}, "
+                               "theta ~ U(30,150) deg, viscosity ratio ~ logU(0.1,10), "
+                               "default_rng(1612); bisection to 0.5 %, 3-decade plain "
+                               "bracket in Bo", "solves": n_eval},
+        "plain_single_solves_per_hour": round(plain_rate, 1),
+        "speedup": round(rate / plain_rate, 2),
+        "batched_plain_solves_per_hour": round(3600.0 * n_eval / t_bp, 1),
+        "probes": {"batched_surrogate": sum(r["probes"] for r in bs),
+                   "batched_plain": sum(r["probes"] for r in bp)},
+        "max_rel_diff_vs_single": round(agree, 5),
+        "surrogate_training": {"solves": len(train), "data_s": round(t_data, 1),
+                               "fit_s": round(t_fit, 2), "val_rmse_log10": sur.sigma_val},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +216,8 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--solves", type=int, default=128,
+                    help="problems per set for --workload solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -139,6 +229,9 @@ def main():
 
     if args.workload == "copy":
         copy_calibration(args.steps, args.warmup)
+        return
+    if args.workload == "solves":
+        print(json.dumps(solves_per_hour(args)), flush=True)
         return
     cfgs, desc = workload(args.workload)
     nf = fluid_nodes(cfgs)

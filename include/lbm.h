@@ -282,6 +282,9 @@ typedef struct {
     double g_lo, g_hi;      /* initial bracket, 0 < g_lo < g_hi */
     int64_t equil_steps;    /* unforced steps before the snapshot */
     int64_t max_steps;      /* step budget of one probe */
+    int64_t min_steps;      /* steps before a probe may be called static; 0: the
+                               options' min_steps (relaxation scales like lambda^2,
+                               so mixed batches set it per problem) */
 } lbm_cp_problem;
 
 typedef struct {

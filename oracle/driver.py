@@ -43,7 +43,7 @@ def _wrap(d, nx):
 
 def solve(engine, problems, **rules):
     """problems: list of dicts with nx, lam, h0, a, tau_w, g_lo, g_hi, max_steps,
-    sigma, rho_bar.  engine: begin_probe(k, g), advance(active, steps),
+    sigma, rho_bar (optional min_steps overriding the rule's).  engine: begin_probe(k, g), advance(active, steps),
     monitors() -> list of dicts (mass, oil_flux, oil_cos, oil_sin, bad_nodes).
     Returns a list of result dicts and, per problem, the probed g values."""
     R = dict(DEFAULT_RULES)
@@ -91,7 +91,8 @@ def solve(engine, problems, **rules):
                     nu_w = (p["tau_w"] - 0.5) / 3.0
                     u_ref = s["g"] * p["h0"] ** 2 / (3.0 * nu_w)
                     U = m["oil_flux"] / m["mass"][0] if m["mass"][0] > 0 else 0.0
-                    if s["t"] >= R["min_steps"] and abs(U) < R["still_frac"] * u_ref:
+                    min_steps = p.get("min_steps") or R["min_steps"]
+                    if s["t"] >= min_steps and abs(U) < R["still_frac"] * u_ref:
                         s["still"] += 1
                     else:
                         s["still"] = 0

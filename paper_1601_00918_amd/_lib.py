@@ -68,7 +68,8 @@ class LbmCpProblem(ctypes.Structure):
     _fields_ = [("geom", LbmGeom), ("fluid", LbmFluid), ("init", LbmInitFields),
                 ("sigma", ctypes.c_double), ("rho_bar", ctypes.c_double),
                 ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
-                ("equil_steps", ctypes.c_int64), ("max_steps", ctypes.c_int64)]
+                ("equil_steps", ctypes.c_int64), ("max_steps", ctypes.c_int64),
+                ("min_steps", ctypes.c_int64)]
 
 
 class LbmCpOptions(ctypes.Structure):
@@ -106,6 +107,10 @@ def load():
     global _LIB
     if _LIB is not None:
         return _LIB
+    # PyTorch (which provides device memory and streams) ships a HIP runtime;
+    # load it first so that the library binds to the same runtime instance
+    # instead of bringing in a second one.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblbm.so is not built (expected at %s); run "
                           "paper_1601_00918_amd/build.py or __graft_entry__.build()" % LIB_PATH)

@@ -222,14 +222,17 @@ def cp_options(**overrides):
     return o
 
 
-def cp_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, keep=None):
-    """Critical-pressure problem from a channel workload dict."""
+def cp_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, keep=None,
+               min_steps=0):
+    """Critical-pressure problem from a channel workload dict (min_steps 0:
+    the options' value)."""
     g, f, i = structs_from_config(cfg, None, keep)
     p = LbmCpProblem()
     p.geom, p.fluid, p.init = g, f, i
     p.sigma, p.rho_bar = float(sigma), float(rho_bar)
     p.g_lo, p.g_hi = float(g_lo), float(g_hi)
     p.equil_steps, p.max_steps = int(equil_steps), int(max_steps)
+    p.min_steps = int(min_steps)
     return p
 
 

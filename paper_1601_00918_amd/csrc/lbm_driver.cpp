@@ -63,7 +63,7 @@ lbm_status check_problem(const lbm_cp_problem& p, int k)
         return fail(LBM_ERR_INVALID, "problem %d: bracket must satisfy 0 < g_lo < g_hi", k);
     if (!(p.sigma > 0.0) || !(p.rho_bar > 0.0))
         return fail(LBM_ERR_INVALID, "problem %d: sigma and rho_bar must be > 0", k);
-    if (p.max_steps <= 0 || p.equil_steps < 0)
+    if (p.max_steps <= 0 || p.equil_steps < 0 || p.min_steps < 0)
         return fail(LBM_ERR_INVALID, "problem %d: bad step counts", k);
     if (!(p.fluid.tau[1] > 0.5))
         return fail(LBM_ERR_INVALID, "problem %d: tau_w must be > 1/2", k);
@@ -99,7 +99,8 @@ Outcome classify(const lbm_cp_problem& p, const lbm_cp_options& o, ProbeState& s
     const double nu_w = (p.fluid.tau[1] - 0.5) / 3.0;
     const double u_ref = s.g * p.geom.h0 * p.geom.h0 / (3.0 * nu_w);
     const double U = m.mass[0] > 0.0 ? m.oil_flux / m.mass[0] : 0.0;
-    if (s.probe_steps >= o.min_steps && std::fabs(U) < o.still_frac * u_ref)
+    const int64_t min_steps = p.min_steps > 0 ? p.min_steps : o.min_steps;
+    if (s.probe_steps >= min_steps && std::fabs(U) < o.still_frac * u_ref)
         ++s.still;
     else
         s.still = 0;

@@ -225,3 +225,21 @@ def mlp_batch(n, seed=7, sizes=(6, 128, 128, 128, 1)):
     X = rng.standard_normal((n, sizes[0])).astype(np.float32)
     t = rng.standard_normal(n).astype(np.float32)
     return X, t
+
+
+def config_cp_set(n, seed, lams=(64,), theta=(30.0, 150.0), log10_m=(-1.0, 1.0)):
+    """Critical-pressure problems: channels of the batch family (h0 = lam/8,
+    a = lam/16, slug 1.5 lam), lam ~ U{lams}, theta ~ U(theta), viscosity
+    ratio M = nu_o / nu_w ~ logU split symmetrically between the relaxation
+    times (tau_o = 1/2 + sqrt(M)/2, tau_w = 1/2 + 1/(2 sqrt(M))), unforced."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        lam = int(rng.choice(lams))
+        th = float(rng.uniform(*theta))
+        m = float(10.0 ** rng.uniform(*log10_m))
+        tau = (0.5 + 0.5 * math.sqrt(m), 0.5 + 0.5 / math.sqrt(m))
+        cfg = config_channel(lam=lam, theta=th, tau=tau)
+        cfg["M"] = m
+        out.append(cfg)
+    return out

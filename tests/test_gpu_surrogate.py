@@ -1,0 +1,61 @@
+"""What the trained surrogate gains over the plain critical-pressure solve,
+on the GPU: train the network on batched plain solves of lambda = 64
+channels, then solve held-out channels both ways.  The surrogate's brackets
+must cost fewer probes and steps and give the same critical forcing (within
+the 0.5 % bisection tolerance of either solve, 1 % apart at most); a wrong
+prediction must be caught by the lazy bracket check and still give the same
+answer."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SIG, RHO = 0.161, 1.03
+RULES = dict(rel_tol=0.005, chunk_steps=500, still_chunks=3)
+
+
+@pytest.fixture(scope="module")
+def trained(gpu_available):
+    from paper_1601_00918_amd import surrogate as sg
+    train = synth.config_cp_set(64, seed=101)
+    res = sg.solve(train, [sg.plain_bracket(c, SIG, RHO) for c in train], SIG, RHO, **RULES)
+    ok = [i for i, r in enumerate(res) if r["flags"] & ~1 == 0]
+    F = np.stack([sg.features(train[i]) for i in ok])
+    y = np.log10([res[i]["bo_crit"] for i in ok])
+    sur = sg.Surrogate(synth.mlp_init(918)).fit(F, y, np.random.default_rng(0), epochs=600)
+    print("trained on %d solves, validation rmse %.4f (log10 Bo)" % (len(ok), sur.sigma_val),
+          flush=True)
+    return sur
+
+
+def test_surrogate_brackets_save_probes_and_keep_the_result(trained):
+    from paper_1601_00918_amd import _lib
+    from paper_1601_00918_amd import surrogate as sg
+    test = synth.config_cp_set(24, seed=202)
+    plain = sg.solve(test, [sg.plain_bracket(c, SIG, RHO) for c in test], SIG, RHO, **RULES)
+    sur = sg.solve(test, trained.brackets(test, SIG, RHO, k=2.0), SIG, RHO, verify_bracket=2,
+                   **RULES)
+    rel = [s["g_crit"] / p["g_crit"] - 1 for s, p in zip(sur, plain)]
+    pp, ps = sum(r["probes"] for r in plain), sum(r["probes"] for r in sur)
+    sp, ss = sum(r["steps"] for r in plain), sum(r["steps"] for r in sur)
+    print("probes %d -> %d, steps %d -> %d, max |g ratio - 1| %.4f" % (
+        pp, ps, sp, ss, max(abs(x) for x in rel)), flush=True)
+    bad = _lib.CP_UNSTABLE | _lib.CP_NOT_CONVERGED
+    assert all(r["flags"] & bad == 0 for r in plain + sur)
+    assert max(abs(x) for x in rel) <= 0.01
+    assert ps <= 0.75 * pp and ss < sp
+
+
+def test_a_wrong_prediction_is_caught_and_corrected(trained):
+    from paper_1601_00918_amd import _lib
+    from paper_1601_00918_amd import surrogate as sg
+    test = synth.config_cp_set(4, seed=303)
+    plain = sg.solve(test, [sg.plain_bracket(c, SIG, RHO) for c in test], SIG, RHO, **RULES)
+    good = trained.brackets(test, SIG, RHO, k=2.0)
+    wrong = [(lo * f, hi * f) for (lo, hi), f in zip(good, (8.0, 1 / 8.0, 5.0, 1 / 5.0))]
+    sur = sg.solve(test, wrong, SIG, RHO, verify_bracket=2, **RULES)
+    for p, s in zip(plain, sur):
+        assert s["flags"] & _lib.CP_WIDENED
+        assert abs(s["g_crit"] / p["g_crit"] - 1) <= 0.01
