@@ -163,11 +163,12 @@ def solves_per_hour(args):
     def batched_sur():
         br = sur.brackets(evals, SIG, RHO, k=2.0)
         return sg.solve(evals, br, SIG, RHO, stream=stream, verify_bracket=2, autotune=1,
-                        **rules)
+                        storage=args.storage, **rules)
     bs, t_bs = timed(batched_sur)
     # 3. batched plain (no surrogate), for the split of the gain
     bp, t_bp = timed(lambda: sg.solve(evals, [sg.plain_bracket(c, SIG, RHO) for c in evals],
-                                      SIG, RHO, stream=stream, autotune=1, **rules))
+                                      SIG, RHO, stream=stream, autotune=1,
+                                      storage=args.storage, **rules))
     log("batched: surrogate %.1f s, plain %.1f s for %d solves" % (t_bs, t_bp, n_eval))
     # 4. plain single-instance solves: a stratified subset, two per lambda
     subset = []
@@ -190,7 +191,7 @@ def solves_per_hour(args):
     return {
         "metric": "critical-pressure solves/hr, batched + surrogate vs plain single-instance",
         "value": round(rate, 1), "unit": "solves/hr", "n_gpus": 1,
-        "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "vs_baseline": None, "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": "channels of the batch family, lambda ~ U{64,128}, "
                                "theta ~ U(30,150) deg, viscosity ratio ~ logU(0.1,10), "
@@ -201,6 +202,7 @@ def solves_per_hour(args):
         "batched_plain_solves_per_hour": round(3600.0 * n_eval / t_bp, 1),
         "probes": {"batched_surrogate": sum(r["probes"] for r in bs),
                    "batched_plain": sum(r["probes"] for r in bp)},
+        # batched (args.storage) vs plain single-instance FP32 on the subset
         "max_rel_diff_vs_single": round(agree, 5),
         "surrogate_training": {"solves": len(train), "data_s": round(t_data, 1),
                                "fit_s": round(t_fit, 2), "val_rmse_log10": sur.sigma_val},
@@ -216,6 +218,8 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tiling", default=None,
+                    help="BX,STRIP for every instance (default: the library's default)")
     ap.add_argument("--solves", type=int, default=128,
                     help="problems per set for --workload solves")
     args = ap.parse_args()
@@ -236,6 +240,9 @@ def main():
     cfgs, desc = workload(args.workload)
     nf = fluid_nodes(cfgs)
     sim = Simulation(cfgs, storage=args.storage)
+    if args.tiling:
+        bx, strip = (int(v) for v in args.tiling.split(","))
+        sim.set_tiling(bx, strip)
     print("bench: %s, %d instances, %d fluid nodes, workspace %.2f GB" %
           (args.workload, len(cfgs), nf, sim.workspace_bytes / 1e9), file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
@@ -259,14 +266,15 @@ def main():
 
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nf
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic(args.storage) if args.workload == "batch" else None
+    traffic = (measured_traffic(args.storage)
+               if args.workload == "batch" and not args.tiling else None)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": desc, "instances": len(cfgs), "fluid_nodes": nf,
-                   "storage": args.storage},
+                   "storage": args.storage, "tiling": list(sim.tiling()[:2])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # measured HBM bytes per launch over the same launch time

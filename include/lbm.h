@@ -219,7 +219,9 @@ lbm_status lbm_fluid_mask(lbm_ctx* ctx, int32_t inst, uint8_t* mask);
  * as separate launches within a step.  Results do not depend on the tiling
  * (bit for bit).  These calls synchronise the stream.
  * lbm_set_tiling sets every instance; lbm_get_tiling returns the values last
- * set for every instance and the total number of work items.
+ * set for every instance and the total number of work items.  Defaults after
+ * lbm_init: FP32 bx = 256 (narrower if every instance is narrower), 8 rows;
+ * 16-bit formats bx = 64, 16 rows.
  */
 lbm_status lbm_set_tiling(lbm_ctx* ctx, int32_t bx, int32_t strip_rows);
 lbm_status lbm_get_tiling(const lbm_ctx* ctx, int32_t* bx, int32_t* strip_rows,
@@ -266,8 +268,12 @@ void lbm_destroy(lbm_ctx* ctx);
  *   static  once at least min_steps have run, |U| < still_frac * U_ref for
  *           still_chunks consecutive chunks and X < creep_frac * lambda, with
  *           U_ref = g h0^2 / (3 nu_w) and nu_w = (tau_w - 1/2) / 3;
- *   at the step budget: moving if X >= creep_frac * lambda, else static
- *           (LBM_CP_UNDECIDED is set);
+ *   at the step budget: moving if the displacement over the second half of
+ *           the budget, X(end) - X(mid), is >= creep_frac * lambda / 2 (the
+ *           same mean velocity as creep_frac * lambda over the whole budget,
+ *           measured after the start-up transient), else static
+ *           (LBM_CP_UNDECIDED is set); X(mid) is taken at the first check at
+ *           or after max_steps / 2;
  *   a non-finite or non-positive density counts as moving (LBM_CP_UNSTABLE).
  * Moving shrinks the bracket from above, static from below; the solve stops
  * when (g_hi - g_lo) / g_lo <= rel_tol and reports g_crit = sqrt(g_lo g_hi)
