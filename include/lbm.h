@@ -268,12 +268,13 @@ void lbm_destroy(lbm_ctx* ctx);
  *   static  once at least min_steps have run, |U| < still_frac * U_ref for
  *           still_chunks consecutive chunks and X < creep_frac * lambda, with
  *           U_ref = g h0^2 / (3 nu_w) and nu_w = (tau_w - 1/2) / 3;
- *   at the step budget: moving if the displacement over the second half of
- *           the budget, X(end) - X(mid), is >= creep_frac * lambda / 2 (the
- *           same mean velocity as creep_frac * lambda over the whole budget,
- *           measured after the start-up transient), else static
- *           (LBM_CP_UNDECIDED is set); X(mid) is taken at the first check at
- *           or after max_steps / 2;
+ *   at the step budget: static (the slug did not advance move_frac * lambda;
+ *           LBM_CP_UNDECIDED is set).  A slug released from rest may hop by
+ *           about a quarter wavelength to the next pinning site at forcings
+ *           well below the critical one and stick there; half a wavelength
+ *           within the budget means it passed a constriction, so "critical"
+ *           is the smallest g that carries the slug half a wavelength within
+ *           max_steps;
  *   a non-finite or non-positive density counts as moving (LBM_CP_UNSTABLE).
  * Moving shrinks the bracket from above, static from below; the solve stops
  * when (g_hi - g_lo) / g_lo <= rel_tol and reports g_crit = sqrt(g_lo g_hi)

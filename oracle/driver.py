@@ -7,10 +7,9 @@ implementation of the probe rules the library documents (moving once the
 slug's centre of oil mass has advanced by move_frac * lambda; static once
 min_steps have run, the mean oil velocity has stayed below still_frac * U_ref
 for still_chunks consecutive checks and the slug has advanced less than
-creep_frac * lambda, U_ref = g h0^2 / (3 nu_w); at the step budget, moving iff it
-advanced creep_frac * lambda / 2 during the second half of the budget (from the
-first check at or after half the budget); a non-physical state counts as
-moving; stop when
+creep_frac * lambda, U_ref = g h0^2 / (3 nu_w); at the step budget, static (it
+did not advance move_frac * lambda); a non-physical state counts as moving;
+stop when
 (g_hi - g_lo) / g_lo <= rel_tol).  It shares no code with the library.
 
 Bracket checks (verify_bracket): 0 trusts the given bracket; 1 probes g_lo
@@ -64,7 +63,7 @@ def solve(engine, problems, **rules):
 
     def begin(k):
         s = st[k]
-        s.update(t=0, X=0.0, prev=x_start[k], still=0, X_mid=None)
+        s.update(t=0, X=0.0, prev=x_start[k], still=0)
         s["history"].append(s["g"])
         engine.begin_probe(k, s["g"])
 
@@ -98,15 +97,11 @@ def solve(engine, problems, **rules):
                         s["still"] += 1
                     else:
                         s["still"] = 0
-                    if s["X_mid"] is None and 2 * s["t"] >= p["max_steps"]:
-                        s["X_mid"] = s["X"]
                     if s["still"] >= R["still_chunks"] and s["X"] < R["creep_frac"] * p["lam"]:
                         verdict = "static"
                     elif s["t"] >= p["max_steps"]:
                         s["flags"] |= UNDECIDED
-                        late = s["X"] - s["X_mid"]
-                        verdict = ("moving" if late >= 0.5 * R["creep_frac"] * p["lam"]
-                                   else "static")
+                        verdict = "static"
             if verdict is None:
                 continue
             s["probes"] += 1

@@ -38,8 +38,6 @@ struct ProbeState {
     // current probe
     int64_t probe_steps = 0;
     double X = 0.0, xc_prev = 0.0;
-    double X_mid = 0.0;  // displacement at the first check past half the budget
-    bool mid_set = false;
     int still = 0;
 };
 
@@ -108,13 +106,9 @@ Outcome classify(const lbm_cp_problem& p, const lbm_cp_options& o, ProbeState& s
         s.still = 0;
     if (s.still >= o.still_chunks && s.X < o.creep_frac * lam)
         return kStatic;
-    if (!s.mid_set && 2 * s.probe_steps >= p.max_steps) {
-        s.X_mid = s.X;
-        s.mid_set = true;
-    }
     if (s.probe_steps >= p.max_steps) {
         flags |= LBM_CP_UNDECIDED;
-        return s.X - s.X_mid >= 0.5 * o.creep_frac * lam ? kMoving : kStatic;
+        return kStatic;  // did not advance move_frac * lambda within the budget
     }
     return kNone;
 }
@@ -145,8 +139,6 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
         ProbeState& s = st[k];
         s.probe_steps = 0;
         s.X = 0.0;
-        s.X_mid = 0.0;
-        s.mid_set = false;
         s.xc_prev = xc0[k];
         s.still = 0;
         return eng.begin_probe(k, s.g);

@@ -56,6 +56,11 @@ def test_a_wrong_prediction_is_caught_and_corrected(trained):
     good = trained.brackets(test, SIG, RHO, k=2.0)
     wrong = [(lo * f, hi * f) for (lo, hi), f in zip(good, (8.0, 1 / 8.0, 5.0, 1 / 5.0))]
     sur = sg.solve(test, wrong, SIG, RHO, verify_bracket=2, **RULES)
+    for c, p, s in zip(test, plain, sur):
+        print("theta %.1f M %.3f  plain %.5e [%d probes, flags %d]  widened %.5e [%d probes, "
+              "flags %d]  ratio %+.4f" % (c["theta"], c["M"], p["g_crit"], p["probes"],
+                                          p["flags"], s["g_crit"], s["probes"], s["flags"],
+                                          s["g_crit"] / p["g_crit"] - 1), flush=True)
     for p, s in zip(plain, sur):
         assert s["flags"] & _lib.CP_WIDENED
         assert abs(s["g_crit"] / p["g_crit"] - 1) <= 0.01
