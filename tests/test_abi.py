@@ -103,3 +103,28 @@ def test_mlp_entry_points_validate_on_the_host():
     null = ctypes.c_void_p(0)
     assert lib.lbm_mlp_forward(null, null, 4, null, null, 0, null) == 1
     assert lib.lbm_mlp_adam(null, null, null, null, 0, 1e-3, 0.9, 0.999, 1e-8, null) == 1
+
+
+def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reports measured traffic only while the step kernel's source is
+    the one the counters were taken with."""
+    import importlib.util
+    import json
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rec = json.load(open(os.path.join(ROOT, "profiles", "step_kernel_batch256_traffic.txt")))
+    t = bench.measured_traffic("f32")
+    expect = 1024.0 * (rec["f32"]["fetch_kib"] * rec["fetch_scale"] +
+                       rec["f32"]["write_kib"] * rec["write_scale"])
+    if t is not None:           # the record matches the current kernel source
+        assert t == expect
+    assert bench.measured_traffic("bf16") is None   # never profiled
+    # a changed kernel source voids the record
+    fake_root = tmp_path
+    (fake_root / "profiles").mkdir()
+    (fake_root / "paper_1601_00918_amd" / "csrc").mkdir(parents=True)
+    (fake_root / "profiles" / "step_kernel_batch256_traffic.txt").write_text(json.dumps(rec))
+    (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_kernels.hip").write_text("// other\n")
+    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    assert bench.measured_traffic("f32") is None
