@@ -136,6 +136,12 @@ def config_droplet(n=128, r=20.0, tau=(1.0, 1.0), G=G_DEFAULT):
                 init=dict(kind="droplet", cx=n / 2, cy=n / 2, r=r))
 
 
+def config_uniform(n=64, tau=(1.0, 1.0), G=G_DEFAULT):
+    """Periodic n x n box of uniform oil (RHO_HI) with dissolved water (RHO_LO)."""
+    return dict(name="uniform", nx=n, ny=n, kind="box", lam=0.0, h0=0.0, a=0.0,
+                tau=tau, G=G, rho_s=(0.0, 0.0), g=(0.0, 0.0), init=dict(kind="uniform"))
+
+
 def config_poiseuille(nx=256, width=64, tau=(0.6, 1.5), g=1e-6, wall_rows=16,
                       core_species=0, G=G_DEFAULT):
     """Two-layer Poiseuille: flat channel of `width` fluid rows, species
@@ -201,6 +207,8 @@ def rho0_of(cfg, mask=None):
         return layers_field(nx, ny, ini["wall_rows"], mask, ini.get("core_species", 0))
     if ini["kind"] == "slug":
         return slug_field(nx, ny, ini["x0"], ini["length"], mask)
+    if ini["kind"] == "uniform":
+        return np.stack([np.full((ny, nx), RHO_HI), np.full((ny, nx), RHO_LO)])
     raise ValueError(ini["kind"])
 
 

@@ -128,3 +128,13 @@ def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_kernels.hip").write_text("// other\n")
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     assert bench.measured_traffic("f32") is None
+
+
+def test_degenerate_and_oversized_inputs_are_rejected():
+    with pytest.raises(_lib.LbmError):
+        binding.lbm_required_bytes([])                      # no instance
+    # an instance whose population block would exceed 32-bit offsets
+    with pytest.raises(_lib.LbmError) as e:
+        binding.lbm_required_bytes([_geom(nx=1 << 16, ny=1 << 12, lam=16384.0, h0=1000.0,
+                                          a=10.0)])
+    assert e.value.status == 1

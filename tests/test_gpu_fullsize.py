@@ -1,0 +1,60 @@
+"""The benchmark workload at full size, in the launch configuration bench.py
+times (the 256-channel batch, default tiling, one launch per step):
+properties that hold for every instance, and sampled instances element by
+element against the oracle.  Plus degenerate inputs."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import field_rel_err, oracle_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def test_full_batch_conserves_mass_and_matches_sampled_instances(gpu_available):
+    from paper_1601_00918_amd import Simulation
+    cfgs = synth.config_batch(n_inst=256, seed=1601)
+    sim = Simulation(cfgs)
+    m0 = sim.monitors()
+    sim.step(100)
+    m1 = sim.monitors()
+    drift = max(abs(b["mass"][s] / a["mass"][s] - 1) for a, b in zip(m0, m1) for s in range(2))
+    bad = sum(m["bad_nodes"] for m in m1)
+    print("256 instances, 100 steps: max mass drift %.2e, bad nodes %d" % (drift, bad), flush=True)
+    # bounce-back and the pull step conserve each species' mass exactly; only
+    # FP32 rounding of the stored populations remains
+    assert bad == 0 and drift <= 1e-6
+    # sampled instances: the first of each of the two smallest wavelengths
+    sampled = [next(k for k, c in enumerate(cfgs) if c["lam"] == lam) for lam in (64, 128)]
+    for k in sampled:
+        L, mask, _ = oracle_lattice(cfgs[k])
+        L.step(100)
+        ref = L.moments()
+        got = sim.moments(k)
+        erho = max(field_rel_err(ref["rho"], got["rho"], mask))
+        ep = max(field_rel_err(ref["p"][None], got["p"][None], mask))
+        print("instance %d (lambda %d): rho %.2e p %.2e" % (k, cfgs[k]["lam"], erho, ep),
+              flush=True)
+        assert erho <= 1e-5 and ep <= 1e-5
+
+
+@pytest.mark.parametrize("storage,G", [("f32", synth.G_DEFAULT), ("f16", 0.0)])
+def test_uniform_mixture_at_rest_stays_at_rest(gpu_available, storage, G):
+    """No density gradient: the interaction force vanishes exactly and the rest
+    equilibrium is a fixed point of the step (up to one rounding per step).
+    In FP32 every node does the same arithmetic, so the state stays uniform
+    to the bit; binary16's stochastic rounding differs per node, which would
+    seed the spinodal instability of the mixture at G = -2.7, so that case
+    runs without interaction."""
+    from paper_1601_00918_amd import Simulation
+    cfg = synth.config_uniform(64, G=G)
+    sim = Simulation([cfg], storage=storage)
+    f0 = sim.populations(0)
+    sim.step(200)
+    f1 = sim.populations(0)
+    mom = sim.moments(0)
+    rel = np.abs(f1 - f0).max() / np.abs(f0).max()
+    umax = np.abs(mom["u"]).max()
+    print(storage, "max |df|/f %.2e  max |u| %.2e" % (rel, umax), flush=True)
+    assert rel <= (1e-6 if storage == "f32" else 1e-3)
+    assert umax <= 1e-6
