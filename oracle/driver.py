@@ -78,16 +78,16 @@ def solve(engine, problems, **rules):
                 continue
             p, s, m = problems[k], st[k], mon[k]
             s["t"] += R["chunk_steps"]
-            verdict = None
+            outcome = None
             if m["bad_nodes"] > 0 or not np.isfinite(m["oil_cos"] + m["oil_sin"] + m["oil_flux"]):
                 s["flags"] |= UNSTABLE
-                verdict = "moving"
+                outcome = "moving"
             else:
                 x = _centre(m, p["nx"])
                 s["X"] += _wrap(x - s["prev"], p["nx"])
                 s["prev"] = x
                 if s["X"] >= R["move_frac"] * p["lam"]:
-                    verdict = "moving"
+                    outcome = "moving"
                 else:
                     nu_w = (p["tau_w"] - 0.5) / 3.0
                     u_ref = s["g"] * p["h0"] ** 2 / (3.0 * nu_w)
@@ -98,14 +98,14 @@ def solve(engine, problems, **rules):
                     else:
                         s["still"] = 0
                     if s["still"] >= R["still_chunks"] and s["X"] < R["creep_frac"] * p["lam"]:
-                        verdict = "static"
+                        outcome = "static"
                     elif s["t"] >= p["max_steps"]:
                         s["flags"] |= UNDECIDED
-                        verdict = "static"
-            if verdict is None:
+                        outcome = "static"
+            if outcome is None:
                 continue
             s["probes"] += 1
-            moving = verdict == "moving"
+            moving = outcome == "moving"
             if s["phase"] == "verify_lo":
                 if moving and s["widen"] < 8:
                     s["widen"] += 1

@@ -76,7 +76,6 @@ template <>
 struct Store<float> {
     static constexpr uint32_t kBytes = 4;  // one species value
     static constexpr uint32_t kPair = 8;   // one (oil, water) pair
-    static constexpr int kPlanes = 9;
     static constexpr float kScale = 1.0f;
     static constexpr bool kRef = false;
     using Pair = f2v;
@@ -110,7 +109,6 @@ template <>
 struct Store<F16Tag> {
     static constexpr uint32_t kBytes = 2;
     static constexpr uint32_t kPair = 4;
-    static constexpr int kPlanes = 10;
     static constexpr float kScale = 36.0f;
     static constexpr bool kRef = true;
     using Pair = uint32_t;
@@ -146,7 +144,6 @@ template <>
 struct Store<BF16Tag> {
     static constexpr uint32_t kBytes = 2;
     static constexpr uint32_t kPair = 4;
-    static constexpr int kPlanes = 10;
     static constexpr float kScale = 36.0f;
     static constexpr bool kRef = true;
     using Pair = uint32_t;
