@@ -8,6 +8,8 @@ Contents
 --------
 lbm_oracle.c    plain FP64 C implementation of the two-component D2Q9 step
 lbm.py          ctypes wrapper and whole-run helpers around it
+lbm3d_oracle.c  the same step on the D3Q19 lattice (tubes, periodic boxes)
+lbm3d.py        ctypes wrapper around it
 young_laplace.py quasi-static Young-Laplace critical pressure (planar, axisymmetric)
 analysis.py     tanh / circle / Laplace fits and the Bond number (Eqs. 11-18)
 driver.py       critical-pressure bisection on top of the oracle step

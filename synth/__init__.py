@@ -251,3 +251,74 @@ def config_cp_set(n, seed, lams=(64,), theta=(30.0, 150.0), log10_m=(-1.0, 1.0))
         cfg["M"] = m
         out.append(cfg)
     return out
+
+
+# ---------------------------------------------------------------- 3-D (D3Q19) --
+# Tube conventions (cell centres at integer coordinates): x periodic with
+# period nx, axis at y_c = (ny - 1) / 2, z_c = (nz - 1) / 2, radius
+# r(x) = r0 + a cos(2 pi x / lam); a node is fluid iff its squared distance to
+# the axis is < r(x)^2.  3-D arrays are [nz][ny][nx] (x fastest).
+def tube_mask(nx, ny, nz, lam, r0, a):
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    y = np.arange(ny, dtype=np.float64)[None, :, None]
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    r = r0 + a * np.cos(2.0 * np.pi * x / lam)
+    d2 = (y - 0.5 * (ny - 1)) ** 2 + (z - 0.5 * (nz - 1)) ** 2
+    return (d2 < r * r).astype(np.uint8)
+
+
+def config_tube(lam=64, r0=10.0, a=4.0, nx=None, ny=None, nz=None, theta=90.0,
+                tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug_len=None, slug_x0=None):
+    """Sinusoidal tube (three wavelengths unless nx is given) with an oil slug."""
+    nx = 3 * lam if nx is None else nx
+    side = int(2 * (r0 + a) + 2)
+    ny = side if ny is None else ny
+    nz = side if nz is None else nz
+    slug_len = int(1.5 * lam) if slug_len is None else slug_len
+    slug_x0 = lam // 4 if slug_x0 is None else slug_x0
+    return dict(name="tube", nx=nx, ny=ny, nz=nz, kind="tube", lam=float(lam), r0=float(r0),
+                a=float(a), tau=tau, G=G, rho_s=wall_potentials_for_angle(theta),
+                g=(g, 0.0, 0.0), theta=theta, init=dict(kind="slug", x0=slug_x0, length=slug_len))
+
+
+def config_box3d(n=32, r=8.0, tau=(1.0, 1.0), G=G_DEFAULT, kind="droplet"):
+    """Periodic n^3 box: an oil sphere of radius r at the centre, or uniform."""
+    init = dict(kind="droplet", cx=n / 2, cy=n / 2, cz=n / 2, r=r) if kind == "droplet" \
+        else dict(kind="uniform")
+    return dict(name="box3d", nx=n, ny=n, nz=n, kind="box3d", tau=tau, G=G,
+                rho_s=(0.0, 0.0), g=(0.0, 0.0, 0.0), init=init)
+
+
+def mask3_of(cfg):
+    if cfg["kind"] == "box3d":
+        return np.ones((cfg["nz"], cfg["ny"], cfg["nx"]), dtype=np.uint8)
+    return tube_mask(cfg["nx"], cfg["ny"], cfg["nz"], cfg["lam"], cfg["r0"], cfg["a"])
+
+
+def rho03_of(cfg, mask=None):
+    """Initial densities [2][nz][ny][nx]: sphere (periodic distance), slug
+    (fluid nodes with x in [x0, x0 + length), periodic) or uniform."""
+    mask = mask3_of(cfg) if mask is None else mask
+    nz, ny, nx = mask.shape
+    ini = cfg["init"]
+    if ini["kind"] == "uniform":
+        oil = np.ones(mask.shape, dtype=bool)
+    elif ini["kind"] == "droplet":
+        x = np.arange(nx, dtype=np.float64)[None, None, :]
+        y = np.arange(ny, dtype=np.float64)[None, :, None]
+        z = np.arange(nz, dtype=np.float64)[:, None, None]
+
+        def pd(v, c, n):
+            d = np.abs(v - c)
+            return np.minimum(d, n - d)
+        oil = (pd(x, ini["cx"], nx) ** 2 + pd(y, ini["cy"], ny) ** 2 +
+               pd(z, ini["cz"], nz) ** 2) < ini["r"] ** 2
+    elif ini["kind"] == "slug":
+        x = np.arange(nx)[None, None, :] * np.ones((nz, ny, 1), dtype=np.int64)
+        oil = np.mod(x - ini["x0"], nx) < ini["length"]
+    else:
+        raise ValueError(ini["kind"])
+    rho = np.empty((2,) + mask.shape)
+    rho[0] = np.where(oil, RHO_HI, RHO_LO)
+    rho[1] = np.where(oil, RHO_LO, RHO_HI)
+    return rho * mask[None]

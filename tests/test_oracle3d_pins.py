@@ -1,0 +1,128 @@
+"""Pins of the D3Q19 oracle (oracle/lbm3d_oracle.c) against what mathematics
+and an independent implementation fix: lattice isotropy, equilibrium and
+regularization moments, a numpy transcription of the step on tiny lattices,
+exact mass conservation in a closed tube, and the Laplace law for 3-D
+droplets."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lbm3d as o3
+from tests import np_bruteforce3d as bf
+
+T0 = 1.0 / 3.0
+
+
+def test_lattice_isotropy():
+    cx, cy, cz, w, opp = o3.lattice()
+    c = np.stack([cx, cy, cz], axis=1).astype(float)
+    assert len(w) == 19 and w.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(c[opp], -c)
+    assert np.allclose(np.einsum('i,ia->a', w, c), 0)
+    assert np.allclose(np.einsum('i,ia,ib->ab', w, c, c), T0 * np.eye(3), atol=1e-15)
+    assert np.allclose(np.einsum('i,ia,ib,ic->abc', w, c, c, c), 0)
+    d = np.eye(3)
+    iso4 = T0 ** 2 * (np.einsum('ab,cd->abcd', d, d) + np.einsum('ac,bd->abcd', d, d) +
+                      np.einsum('ad,bc->abcd', d, d))
+    assert np.allclose(np.einsum('i,ia,ib,ic,id->abcd', w, c, c, c, c), iso4, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_equilibrium_moments(seed):
+    """Eq. 7 on D3Q19: mass rho, momentum rho u and momentum flux
+    rho T0 I + rho u u exactly (the cubic terms cancel in the first moment by
+    fourth-order isotropy and vanish in the even moments)."""
+    rng = np.random.default_rng(seed)
+    rho = 0.3 + rng.random()
+    u = 0.1 * rng.standard_normal(3)
+    feq = o3.equilibrium(rho, *u)
+    cx, cy, cz, w, _ = o3.lattice()
+    c = np.stack([cx, cy, cz], axis=1).astype(float)
+    assert feq.sum() == pytest.approx(rho, rel=1e-14)
+    assert np.allclose(c.T @ feq, rho * u, rtol=0, atol=1e-15)
+    assert np.allclose(np.einsum('ia,ib,i->ab', c, c, feq),
+                       rho * T0 * np.eye(3) + rho * np.outer(u, u), rtol=0, atol=1e-15)
+
+
+def test_regularized_part_reproduces_the_nonequilibrium_flux():
+    rng = np.random.default_rng(4)
+    f = 0.05 + 0.02 * rng.random(19)
+    feq = o3.equilibrium(f.sum(), 0.02, -0.01, 0.03)
+    fneq = o3.regularize(f, feq)
+    cx, cy, cz, _, _ = o3.lattice()
+    c = np.stack([cx, cy, cz], axis=1).astype(float)
+    P = np.einsum('ia,ib,i->ab', c, c, f - feq)
+    assert abs(fneq.sum()) < 1e-15 and np.allclose(c.T @ fneq, 0, atol=1e-15)
+    assert np.allclose(np.einsum('ia,ib,i->ab', c, c, fneq), P, atol=1e-15)
+
+
+def _to_bf(f):
+    """oracle direction order -> the brute force's velocity order."""
+    cx, cy, cz, _, _ = o3.lattice()
+    c = np.stack([cx, cy, cz], axis=1)
+    perm = [int(np.nonzero((c == v).all(axis=1))[0][0]) for v in bf.VEL]
+    return f[:, perm]
+
+
+@pytest.mark.parametrize("case", ["box", "tube"])
+def test_step_matches_independent_numpy_transcription(case):
+    rng = np.random.default_rng(7)
+    if case == "box":
+        nz, ny, nx = 3, 4, 5
+        mask = np.ones((nz, ny, nx), dtype=np.uint8)
+        periodic = True
+    else:
+        nz, ny, nx = 5, 6, 6
+        mask = (rng.random((nz, ny, nx)) < 0.75).astype(np.uint8)
+        periodic = False
+    p = o3.Params3(nx, ny, nz, tau=(0.8, 1.3), G=-2.7, rho_s=(0.3, 0.6),
+                   g=(1e-3, -2e-4, 5e-4), periodic_yz=periodic)
+    w = o3.lattice()[3]
+    base = 0.03 + 0.97 * rng.random((2, 1, nz, ny, nx))
+    f = w[None, :, None, None, None] * base * (1 + 0.05 * rng.uniform(-1, 1, (2, 19, nz, ny, nx)))
+    f *= mask[None, None]
+    got = f.copy()
+    for _ in range(3):
+        got, bad = o3.step_once(p, mask, got)
+        assert bad == 0
+    ref = bf.run(_to_bf(f), mask, (0.8, 1.3), -2.7, (0.3, 0.6), (1e-3, -2e-4, 5e-4), 3,
+                 periodic)
+    assert np.abs(_to_bf(got) - ref).max() < 1e-14
+
+
+def test_closed_tube_conserves_each_species_mass():
+    cfg = synth.config_tube(lam=32, r0=6.0, a=2.0, theta=60.0, g=2e-4)
+    mask = synth.mask3_of(cfg)
+    p = o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                   rho_s=cfg["rho_s"], g=cfg["g"])
+    L = o3.Lattice3(p, mask, synth.rho03_of(cfg, mask))
+    m0 = L.moments()["mon"][:2]
+    L.step(200)
+    m1 = L.moments()["mon"][:2]
+    assert np.allclose(m1, m0, rtol=1e-12, atol=0)
+
+
+def test_laplace_law_for_3d_droplets():
+    """Delta p = 2 sigma / R (Eq. 11 in 3-D): the jump between the droplet
+    centre and the far field is linear in 1/R through the origin."""
+    inv_r, dp = [], []
+    for r in (5.0, 6.5, 8.0):
+        cfg = synth.config_box3d(n=24, r=r)
+        mask = synth.mask3_of(cfg)
+        p = o3.Params3(24, 24, 24, tau=cfg["tau"], G=cfg["G"], periodic_yz=True)
+        L = o3.Lattice3(p, mask, synth.rho03_of(cfg, mask))
+        L.step(1200)
+        m = L.moments()
+        rho_o = m["rho"][0]
+        R = (3.0 * (rho_o > 0.5).sum() / (4.0 * np.pi)) ** (1.0 / 3.0)  # from the volume
+        pr = m["p"]
+        dp.append(pr[10:14, 10:14, 10:14].mean() - pr[0:3, 0:3, 0:3].mean())
+        inv_r.append(1.0 / R)
+    slope, icpt = np.polyfit(inv_r, dp, 1)
+    fit = np.polyval([slope, icpt], inv_r)
+    resid = np.abs(fit - dp).max() / max(dp)
+    print("1/R", inv_r, "dp", dp, "slope", slope, "intercept", icpt)
+    assert slope > 0 and resid < 0.02
+    assert abs(icpt) < 0.1 * min(dp)
