@@ -23,6 +23,9 @@ sys.path.insert(0, ROOT)
 METRIC = "2-comp MLUPS & % HBM roofline; critical-pressure solves/hr batched vs plain"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f32": 144, "f16": 80, "bf16": 80}
+# D3Q19: 2 species x 19 populations (+ the reference-density pair of the
+# 16-bit formats) read and written once per fluid-node update.
+BYTES_PER_NODE_3D = {"f32": 304, "f16": 160, "bf16": 160}
 
 
 def workload(name):
@@ -44,6 +47,93 @@ def workload(name):
     else:
         raise SystemExit("unknown workload %r" % name)
     return cfgs, desc
+
+
+def tube_config():
+    """The D3Q19 tube: 512 x 128 x 128, r(x) = 40 + 16 cos(2 pi x / 256), an oil
+    slug of 384 nodes starting at x = 64."""
+    import synth
+    return synth.config_tube(lam=256, r0=40.0, a=16.0, nx=512, ny=128, nz=128, theta=60.0,
+                             tau=(1.0, 1.0), g=1e-6, slug_len=384, slug_x0=64)
+
+
+def cpu_baseline_tube(seconds):
+    """The FP64 D3Q19 oracle on a bounded sample: a tube of the same shape
+    family scaled down by 4 (128 x 34 x 34, r(x) = 10 + 4 cos(2 pi x / 64)),
+    stepped until about `seconds` have passed."""
+    import synth
+    from oracle import lbm3d as o3
+    from oracle import lbm as orc
+
+    cfg = synth.config_tube(lam=64, r0=10.0, a=4.0, nx=128, ny=34, nz=34, theta=60.0,
+                            tau=(1.0, 1.0), g=1e-6, slug_len=96, slug_x0=16)
+    mask = synth.mask3_of(cfg)
+    p = o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                   rho_s=cfg["rho_s"], g=cfg["g"])
+    L = o3.Lattice3(p, mask, synth.rho03_of(cfg, mask))
+    nf = int(mask.sum())
+    L.step(1)
+    t0 = time.perf_counter()
+    L.step(3)
+    dt = time.perf_counter() - t0
+    n = max(3, int(seconds / max(dt / 3, 1e-6)))
+    t0 = time.perf_counter()
+    L.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": nf * n / dt / 1e6, "unit": "MLUPS", "cores": orc.threads_used(),
+            "kind": "oracle",
+            "sample": "FP64 D3Q19 oracle, the tube scaled down by 4 (128x34x34, %d fluid nodes), "
+                      "%d steps in %.1f s" % (nf, n, dt)}
+
+
+def bench_tube(args):
+    """MLUPS of the D3Q19 step on the 512 x 128 x 128 sinusoidal tube."""
+    import torch
+    import synth
+    from paper_1601_00918_amd.binding3d import Simulation3D
+
+    cfg = tube_config()
+    nf = int(synth.mask3_of(cfg).sum())
+    sim = Simulation3D(cfg, storage=args.storage)
+    if args.tiling:
+        bx, by, strip = (int(v) for v in args.tiling.split(","))
+        sim.set_tiling(bx, by, strip)
+    print("bench: tube3d, %d fluid nodes, workspace %.2f GB, tiling %s" %
+          (nf, sim.workspace_bytes / 1e9, sim.tiling()), file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    mlups = nf * args.steps / (ms / 1e3) / 1e6
+    mon = sim.monitors()
+    print("bench: %.4f ms/step (events), wall %.3f s, %.0f MLUPS, bad nodes %d" %
+          (ms_per_step, wall, mlups, mon["bad_nodes"]), file=sys.stderr, flush=True)
+    bytes_per_launch = BYTES_PER_NODE_3D[args.storage] * nf
+    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": "D3Q19 sinusoidal tube 512x128x128, r(x) = 40 + 16 cos(2 pi x/256), "
+                               "oil slug 384, theta 60 deg, g = 1e-6",
+                   "fluid_nodes": nf, "storage": args.storage, "tiling": list(sim.tiling()[:3])},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_tube(args.cpu_seconds)
+    return out
 
 
 def fluid_nodes(cfgs):
@@ -77,6 +167,10 @@ def cpu_baseline(seconds):
                       "%d steps in %.1f s" % (nf, n, dt)}
 
 
+# Sources of the D2Q9 step kernel; the counter record names their hash.
+KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_store.h")
+
+
 def measured_traffic(storage):
     """HBM bytes per step launch from the committed FETCH_SIZE / WRITE_SIZE
     counter record of the 256-channel batch, scaled by the copy-kernel
@@ -84,10 +178,11 @@ def measured_traffic(storage):
     were taken or the format was not profiled."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "step_kernel_batch256_traffic.txt")
-    src = os.path.join(ROOT, "paper_1601_00918_amd", "csrc", "lbm_kernels.hip")
+    csrc = os.path.join(ROOT, "paper_1601_00918_amd", "csrc")
     try:
         rec = json.load(open(rec_path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                    for f in KERNEL_SOURCES)).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != h or storage not in rec:
@@ -219,7 +314,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tiling", default=None,
-                    help="BX,STRIP for every instance (default: the library's default)")
+                    help="BX,STRIP for every instance (default: the library's default); "
+                         "BX,BY,STRIP for --workload tube3d")
     ap.add_argument("--solves", type=int, default=128,
                     help="problems per set for --workload solves")
     args = ap.parse_args()
@@ -236,6 +332,9 @@ def main():
         return
     if args.workload == "solves":
         print(json.dumps(solves_per_hour(args)), flush=True)
+        return
+    if args.workload == "tube3d":
+        print(json.dumps(bench_tube(args)), flush=True)
         return
     cfgs, desc = workload(args.workload)
     nf = fluid_nodes(cfgs)

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/lbm.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/lbm.h, include/lbm_mlp.h and
+include/lbm3d.h (argument marshalling only).
 
 Loading fails loudly when ``liblbm.so`` has not been built: there is no
 fallback implementation of any entry point.
@@ -26,7 +27,14 @@ EXPORTED = [
     "lbm_cp_required_bytes", "lbm_critical_pressure", "lbm_cp_drive",
     "lbm_set_instance_tiling", "lbm_get_instance_tiling", "lbm_autotune",
     "lbm_mlp_workspace_bytes", "lbm_mlp_forward", "lbm_mlp_backward", "lbm_mlp_adam",
+    "lbm3d_required_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_time", "lbm3d_set_fluid",
+    "lbm3d_moments", "lbm3d_monitors", "lbm3d_get_populations", "lbm3d_fluid_mask",
+    "lbm3d_set_tiling", "lbm3d_get_tiling", "lbm3d_snapshot_save", "lbm3d_snapshot_restore",
+    "lbm3d_destroy",
 ]
+
+GEOM3_BOX, GEOM3_TUBE, GEOM3_MASK = 0, 1, 2
+INIT3_UNIFORM, INIT3_DROPLET, INIT3_SLUG = 0, 1, 3
 
 OPT_SNAPSHOT = 0x100
 CP_UNDECIDED, CP_UNSTABLE, CP_WIDENED, CP_NOT_CONVERGED = 1, 2, 4, 8
@@ -86,6 +94,24 @@ class LbmCpResult(ctypes.Structure):
                 ("g_crit", ctypes.c_double), ("bo_crit", ctypes.c_double),
                 ("probes", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("steps", ctypes.c_int64)]
+
+
+class Lbm3dGeom(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("lam", ctypes.c_double), ("r0", ctypes.c_double),
+                ("a", ctypes.c_double), ("mask", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class Lbm3dFluid(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double * 2), ("G", ctypes.c_double),
+                ("rho_s", ctypes.c_double * 2), ("g", ctypes.c_double * 3)]
+
+
+class Lbm3dInitFields(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double),
+                ("r", ctypes.c_double), ("x0", ctypes.c_double), ("length", ctypes.c_double)]
 
 
 CP_BEGIN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double)
@@ -159,9 +185,29 @@ def load():
     lib.lbm_mlp_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
     fl = ctypes.c_float
     lib.lbm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
+    lib.lbm3d_required_bytes.argtypes = [ctypes.POINTER(Lbm3dGeom), i32, ctypes.POINTER(sz)]
+    lib.lbm3d_init.argtypes = [ctypes.POINTER(Lbm3dGeom), ctypes.POINTER(Lbm3dFluid),
+                               ctypes.POINTER(Lbm3dInitFields), i32, vp, sz, vp,
+                               ctypes.POINTER(vp)]
+    lib.lbm3d_step.argtypes = [vp, i64]
+    lib.lbm3d_time.argtypes = [vp]
+    lib.lbm3d_time.restype = i64
+    lib.lbm3d_set_fluid.argtypes = [vp, ctypes.POINTER(Lbm3dFluid)]
+    lib.lbm3d_moments.argtypes = [vp, dp, dp, dp, ctypes.POINTER(LbmMonitor)]
+    lib.lbm3d_monitors.argtypes = [vp, ctypes.POINTER(LbmMonitor)]
+    lib.lbm3d_get_populations.argtypes = [vp, dp]
+    lib.lbm3d_fluid_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    lib.lbm3d_set_tiling.argtypes = [vp, i32, i32, i32]
+    lib.lbm3d_get_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.lbm3d_snapshot_save.argtypes = [vp]
+    lib.lbm3d_snapshot_restore.argtypes = [vp]
+    lib.lbm3d_destroy.argtypes = [vp]
+    lib.lbm3d_destroy.restype = None
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy",
-                        "lbm_cp_default_options", "lbm_mlp_workspace_bytes"):
+                        "lbm_cp_default_options", "lbm_mlp_workspace_bytes", "lbm3d_time",
+                        "lbm3d_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib

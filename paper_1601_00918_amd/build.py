@@ -1,31 +1,47 @@
-"""Build the HIP shared library ``liblbm.so`` (gfx950) in-tree with hipcc."""
+"""Build the HIP shared library ``liblbm.so`` (gfx950) in-tree with hipcc.
+
+Each source is compiled to an object in ``_build/`` (in parallel), then the
+objects are linked into ``liblbm.so`` next to this file."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_driver.cpp", "lbm_mlp.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_driver.cpp", "lbm_mlp.hip",
+           "lbm3d_kernels.hip", "lbm3d_runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 
 
+def _compile(src, verbose):
+    obj = os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+    cmd = [HIPCC, *FLAGS, "-c", "-x", "hip", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source for gfx950 and link liblbm.so; returns its path."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        objs = list(pool.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS]
-    for src in srcs:
-        cmd += ["-x", "hip", src]
-    cmd += ["-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

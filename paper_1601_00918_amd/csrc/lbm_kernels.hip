@@ -26,12 +26,15 @@
 // node's own density, so a density is bitwise the same whichever workgroup
 // computes it.  Solid neighbours enter the ring as the wall potentials rho_s.
 #include "lbm_internal.h"
+#include "lbm_store.h"
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 namespace lbm {
 namespace {
+
+using namespace dev;
 
 constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -63,121 +66,8 @@ constexpr float kInvW36[9] = {1.f / 16.f, 0.25f, 0.25f, 0.25f, 0.25f, 1.f, 1.f, 
 // 36 (36 f_i = (36 w_i)(R + d_i)), so the weights are the exact factors 16,
 // 4 and 1; the regularized collision is linear in the moments and runs
 // unchanged on scaled values; the interaction constant, the wall potentials
-// and the FP64 monitors and exports take the scale into account.
-struct F16Tag {};
-struct BF16Tag {};
-
-typedef float f2v __attribute__((ext_vector_type(2)));
-
-template <typename T>
-struct Store;
-
-template <>
-struct Store<float> {
-    static constexpr uint32_t kBytes = 4;  // one species value
-    static constexpr uint32_t kPair = 8;   // one (oil, water) pair
-    static constexpr float kScale = 1.0f;
-    static constexpr bool kRef = false;
-    using Pair = f2v;
-    __device__ static Pair load(const char* p) { return *reinterpret_cast<const f2v*>(p); }
-    __device__ static void unpack(Pair v, float& a, float& b)
-    {
-        a = v.x;
-        b = v.y;
-    }
-    __device__ static void put(char* p, float a, float b)
-    {
-        f2v v;
-        v.x = a;
-        v.y = b;
-        __builtin_nontemporal_store(v, reinterpret_cast<f2v*>(p));
-    }
-};
-
-__device__ __forceinline__ void put32(char* p, uint32_t b)
-{
-    __builtin_nontemporal_store(b, reinterpret_cast<uint32_t*>(p));
-}
-
-__device__ __forceinline__ float h2f(uint32_t b)
-{
-    return __half2float(__ushort_as_half((unsigned short)b));
-}
-__device__ __forceinline__ uint32_t f2h_rn(float v) { return __half_as_ushort(__float2half_rn(v)); }
-
-template <>
-struct Store<F16Tag> {
-    static constexpr uint32_t kBytes = 2;
-    static constexpr uint32_t kPair = 4;
-    static constexpr float kScale = 36.0f;
-    static constexpr bool kRef = true;
-    using Pair = uint32_t;
-    __device__ static Pair load(const char* p) { return *reinterpret_cast<const uint32_t*>(p); }
-    __device__ static void unpack(Pair v, float& a, float& b)
-    {
-        a = h2f(v & 0xffffu);
-        b = h2f(v >> 16);
-    }
-    __device__ static float val(uint32_t b) { return h2f(b); }
-    __device__ static uint32_t rne(float v) { return f2h_rn(v); }
-    // Stochastic rounding to binary16: add uniform random bits below the
-    // target precision to the magnitude and truncate (exact conversion after).
-    __device__ static uint32_t sr(float v, uint32_t rnd)
-    {
-        const uint32_t u = __float_as_uint(v);
-        const uint32_t sign = u & 0x80000000u;
-        uint32_t a = u & 0x7fffffffu;
-        const int e = (int)(a >> 23) - 127;
-        if (e >= -14) {  // binary16 normal range: 13 bits below the last place
-            a = (a + (rnd & 0x1fffu)) & ~0x1fffu;
-        } else if (e >= -24) {  // subnormal: the last place is 2^-24
-            const uint32_t m = (1u << (uint32_t)(-1 - e)) - 1u;
-            a = (a + (rnd & m)) & ~m;
-        } else {  // below 2^-24: 0 or 2^-24 with probability |v| / 2^-24
-            a = (float)(rnd >> 8) * 0x1p-24f < __uint_as_float(a) * 0x1p24f ? 0x33800000u : 0u;
-        }
-        return f2h_rn(__uint_as_float(sign | a));
-    }
-};
-
-template <>
-struct Store<BF16Tag> {
-    static constexpr uint32_t kBytes = 2;
-    static constexpr uint32_t kPair = 4;
-    static constexpr float kScale = 36.0f;
-    static constexpr bool kRef = true;
-    using Pair = uint32_t;
-    __device__ static Pair load(const char* p) { return *reinterpret_cast<const uint32_t*>(p); }
-    __device__ static void unpack(Pair v, float& a, float& b)
-    {
-        a = __uint_as_float(v << 16);
-        b = __uint_as_float(v & 0xffff0000u);
-    }
-    __device__ static float val(uint32_t b) { return __uint_as_float(b << 16); }
-    // Round to nearest even (the deviations are finite by construction).
-    __device__ static uint32_t rne(float v)
-    {
-        const uint32_t u = __float_as_uint(v);
-        return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    }
-    __device__ static uint32_t sr(float v, uint32_t rnd)
-    {
-        return (__float_as_uint(v) + (rnd & 0xffffu)) >> 16;
-    }
-};
-
-// Integer hash (Wellons' "lowbias32", from his 2018 hash-prospector search):
-// a bijection of 32-bit integers with low bias, used as a counter-based
-// generator for the stochastic rounding bits.
-__device__ __forceinline__ uint32_t lowbias32(uint32_t x)
-{
-    x ^= x >> 16;
-    x *= 0x7feb352du;
-    x ^= x >> 15;
-    x *= 0x846ca68bu;
-    x ^= x >> 16;
-    return x;
-}
+// and the FP64 monitors and exports take the scale into account.  The format
+// types (Store<float>, Store<F16Tag>, Store<BF16Tag>) live in lbm_store.h.
 
 // Encode the scaled post-collision populations F[s][9] of both species at one
 // node (scaled densities rho36[s]) into the 16-bit deviation format and store
@@ -212,11 +102,6 @@ __device__ __forceinline__ void encode_node(const float (&F)[2][9], const float 
         b0[s] = S::sr(((rho36[s] - 36.0f * R[s]) - msum[s]) * (1.0f / 16.0f), rnd[s]);
     put32(dst, b0[0] | (b0[1] << 16));
     put32(dst + 9 * plane, rb[0] | (rb[1] << 16));
-}
-
-__device__ __forceinline__ int wrapi(int a, int n)
-{
-    return a < 0 ? a + n : (a >= n ? a - n : a);
 }
 
 __device__ __forceinline__ bool in_run(Col c, int y)
@@ -324,24 +209,6 @@ __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy
     pair(vy, b1, g2, out[2], out[4]);
     pair(vx + vy, b5, g5, out[5], out[7]);
     pair(vy - vx, b5, g6, out[6], out[8]);
-}
-
-__device__ __forceinline__ int remap_xcd(int b, int n)
-{
-    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of items so neighbouring strips share one L2.
-    const int q = n >> 3, rem = n & 7;
-    const int xcd = b & 7, slot = b >> 3;
-    const int start = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
-    return start + slot;
-}
-
-// Barrier that orders LDS only: global loads of the next row stay in flight.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Byte offsets (relative to the instance's first byte) of the 9 pulled

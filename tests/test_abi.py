@@ -19,7 +19,7 @@ def _declared_functions():
         if h.endswith(".h"):
             text = open(os.path.join(ROOT, "include", h)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names.update(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+            names.update(re.findall(r"\b(lbm(?:3d)?_[a-z_0-9]+)\s*\(", text))
     return sorted(names)
 
 
@@ -126,6 +126,7 @@ def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     (fake_root / "paper_1601_00918_amd" / "csrc").mkdir(parents=True)
     (fake_root / "profiles" / "step_kernel_batch256_traffic.txt").write_text(json.dumps(rec))
     (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_kernels.hip").write_text("// other\n")
+    (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_store.h").write_text("// other\n")
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     assert bench.measured_traffic("f32") is None
 
