@@ -119,6 +119,8 @@ def bench_tube(args):
           (ms_per_step, wall, mlups, mon["bad_nodes"]), file=sys.stderr, flush=True)
     bytes_per_launch = BYTES_PER_NODE_3D[args.storage] * nf
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    traffic = (None if args.tiling else
+               measured_traffic(args.storage, "step3_kernel_tube_traffic.txt", KERNEL3_SOURCES))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -128,7 +130,10 @@ def bench_tube(args):
                                "oil slug 384, theta 60 deg, g = 1e-6",
                    "fluid_nodes": nf, "storage": args.storage, "tiling": list(sim.tiling()[:3])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (round(traffic / (ms_per_step / 1e3) / 1e9, 1)
+                                 if traffic else None),
+                     "traffic_bytes_per_launch": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu:
@@ -169,20 +174,22 @@ def cpu_baseline(seconds):
 
 # Sources of the D2Q9 step kernel; the counter record names their hash.
 KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_store.h")
+KERNEL3_SOURCES = ("lbm3d_kernels.hip", "lbm_store.h")
 
 
-def measured_traffic(storage):
-    """HBM bytes per step launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter record of the 256-channel batch, scaled by the copy-kernel
-    calibration; None when the kernel source has changed since the counters
-    were taken or the format was not profiled."""
+def measured_traffic(storage, record="step_kernel_batch256_traffic.txt",
+                     sources=KERNEL_SOURCES):
+    """HBM bytes per step launch from a committed FETCH_SIZE / WRITE_SIZE
+    counter record (the 256-channel batch by default), scaled by the
+    copy-kernel calibration; None when the kernel source has changed since the
+    counters were taken or the format was not profiled."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "step_kernel_batch256_traffic.txt")
+    rec_path = os.path.join(ROOT, "profiles", record)
     csrc = os.path.join(ROOT, "paper_1601_00918_amd", "csrc")
     try:
         rec = json.load(open(rec_path))
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                    for f in KERNEL_SOURCES)).hexdigest()
+                                    for f in sources)).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != h or storage not in rec:

@@ -122,7 +122,7 @@ lbm_status lbm3d_fluid_mask(lbm3d_ctx* ctx, uint8_t* mask);
 
 /* Tiling of the step kernel: one workgroup advances a tile of bx x by nodes
  * (x, y) through a strip of strip_planes planes along z.  (bx, by) is one of
- * (32, 16) (default), (64, 8), (32, 8); strip_planes >= 4 (default 16).
+ * (32, 16) (default), (64, 8), (32, 8); strip_planes >= 4 (default 8).
  * Results do not depend on the tiling (bit for bit).  Synchronises. */
 lbm_status lbm3d_set_tiling(lbm3d_ctx* ctx, int32_t bx, int32_t by, int32_t strip_planes);
 lbm_status lbm3d_get_tiling(const lbm3d_ctx* ctx, int32_t* bx, int32_t* by,
@@ -135,6 +135,40 @@ lbm_status lbm3d_snapshot_restore(lbm3d_ctx* ctx);
 
 /* Release the context (not the caller's workspace or stream). */
 void lbm3d_destroy(lbm3d_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Critical pressure in the tube (Sec. 3.4): the smallest body acceleration g
+ * along +x that mobilises the oil slug, by the bisection and the probe
+ * classification of lbm_critical_pressure (lbm.h), with the tube's lambda,
+ * mean radius r0 (in place of h0: U_ref = g r0^2 / (3 nu_w)), a and nx, and
+ * Bo = rho_bar g_crit L D / sigma (Eq. 15) with L = nx and D = r0 - a, the
+ * neck radius (the length unit of the paper's tube).  Every problem has its
+ * own context; they are equilibrated, snapshotted and probed on the caller's
+ * stream, one after another within each chunk of steps.  opts->storage
+ * selects the population format; opts->autotune is ignored.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    lbm3d_geom geom;         /* LBM3D_GEOM_TUBE */
+    lbm3d_fluid fluid;       /* tau, G, rho_s; g is set by the solver */
+    lbm3d_init_fields init;  /* usually LBM3D_INIT_SLUG */
+    double sigma;            /* surface tension used for Bo */
+    double rho_bar;          /* density used for Bo */
+    double g_lo, g_hi;       /* initial bracket, 0 < g_lo < g_hi */
+    int64_t equil_steps;     /* unforced steps before the snapshot */
+    int64_t max_steps;       /* step budget of one probe */
+    int64_t min_steps;       /* steps before a probe may be called static (0: options) */
+} lbm3d_cp_problem;
+
+/* Workspace bytes lbm3d_critical_pressure needs for these problems in this
+ * storage format (lbm_storage). */
+lbm_status lbm3d_cp_required_bytes(const lbm3d_cp_problem* probs, int32_t n, int32_t storage,
+                                   size_t* bytes);
+
+/* Solve n tube problems; results[n] is caller-owned.  Synchronises. */
+lbm_status lbm3d_critical_pressure(const lbm3d_cp_problem* probs, int32_t n,
+                                   const lbm_cp_options* opts, void* device_workspace,
+                                   size_t workspace_bytes, void* hip_stream,
+                                   lbm_cp_result* results);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,7 @@ EXPORTED = [
     "lbm3d_required_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_time", "lbm3d_set_fluid",
     "lbm3d_moments", "lbm3d_monitors", "lbm3d_get_populations", "lbm3d_fluid_mask",
     "lbm3d_set_tiling", "lbm3d_get_tiling", "lbm3d_snapshot_save", "lbm3d_snapshot_restore",
-    "lbm3d_destroy",
+    "lbm3d_destroy", "lbm3d_cp_required_bytes", "lbm3d_critical_pressure",
 ]
 
 GEOM3_BOX, GEOM3_TUBE, GEOM3_MASK = 0, 1, 2
@@ -112,6 +112,14 @@ class Lbm3dInitFields(ctypes.Structure):
                 ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double),
                 ("r", ctypes.c_double), ("x0", ctypes.c_double), ("length", ctypes.c_double)]
+
+
+class Lbm3dCpProblem(ctypes.Structure):
+    _fields_ = [("geom", Lbm3dGeom), ("fluid", Lbm3dFluid), ("init", Lbm3dInitFields),
+                ("sigma", ctypes.c_double), ("rho_bar", ctypes.c_double),
+                ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
+                ("equil_steps", ctypes.c_int64), ("max_steps", ctypes.c_int64),
+                ("min_steps", ctypes.c_int64)]
 
 
 CP_BEGIN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double)
@@ -202,6 +210,11 @@ def load():
                                      ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.lbm3d_snapshot_save.argtypes = [vp]
     lib.lbm3d_snapshot_restore.argtypes = [vp]
+    lib.lbm3d_cp_required_bytes.argtypes = [ctypes.POINTER(Lbm3dCpProblem), i32, i32,
+                                            ctypes.POINTER(sz)]
+    lib.lbm3d_critical_pressure.argtypes = [ctypes.POINTER(Lbm3dCpProblem), i32,
+                                            ctypes.POINTER(LbmCpOptions), vp, sz, vp,
+                                            ctypes.POINTER(LbmCpResult)]
     lib.lbm3d_destroy.argtypes = [vp]
     lib.lbm3d_destroy.restype = None
     for name in EXPORTED:

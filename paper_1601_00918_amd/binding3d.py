@@ -8,8 +8,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (GEOM3_BOX, GEOM3_MASK, GEOM3_TUBE, INIT3_DROPLET, INIT3_SLUG, INIT3_UNIFORM,
-                   OPT_SNAPSHOT, STORE_BF16, STORE_F16, STORE_F32, Lbm3dFluid, Lbm3dGeom,
-                   Lbm3dInitFields, LbmMonitor, check)
+                   OPT_SNAPSHOT, STORE_BF16, STORE_F16, STORE_F32, Lbm3dCpProblem, Lbm3dFluid,
+                   Lbm3dGeom, Lbm3dInitFields, LbmCpOptions, LbmCpResult, LbmMonitor, check)
 
 _GEOM_KINDS = {"box3d": GEOM3_BOX, "box": GEOM3_BOX, "tube": GEOM3_TUBE, "mask": GEOM3_MASK}
 _INIT_KINDS = {"uniform": INIT3_UNIFORM, "droplet": INIT3_DROPLET, "slug": INIT3_SLUG}
@@ -160,6 +160,46 @@ def lbm3d_snapshot_restore(ctx):
 
 def lbm3d_destroy(ctx):
     _lib.load().lbm3d_destroy(ctx)
+
+
+def cp3_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, min_steps=0):
+    """Tube critical-pressure problem from a tube workload dict."""
+    g, f, i = structs3_from_config(cfg)
+    p = Lbm3dCpProblem()
+    p.geom, p.fluid, p.init = g, f, i
+    p.sigma, p.rho_bar = float(sigma), float(rho_bar)
+    p.g_lo, p.g_hi = float(g_lo), float(g_hi)
+    p.equil_steps, p.max_steps = int(equil_steps), int(max_steps)
+    p.min_steps = int(min_steps)
+    return p
+
+
+def lbm3d_cp_required_bytes(problems, storage="f32"):
+    n = ctypes.c_size_t()
+    arr = (Lbm3dCpProblem * len(problems))(*problems)
+    check(_lib.load().lbm3d_cp_required_bytes(arr, len(problems), _STORAGE[storage],
+                                              ctypes.byref(n)), "lbm3d_cp_required_bytes")
+    return n.value
+
+
+def lbm3d_critical_pressure(problems, opts=None, device="cuda", stream=None):
+    """Solve tube problems on the GPU; returns a list of result dicts."""
+    import torch  # device memory and streams only
+
+    from .binding import _result_dict, cp_options
+    o = opts if opts is not None else cp_options()
+    storage = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16"}[o.storage]
+    nbytes = lbm3d_cp_required_bytes(problems, storage)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    st = stream if stream is not None else torch.cuda.Stream(ws.device)
+    res = (LbmCpResult * len(problems))()
+    arr = (Lbm3dCpProblem * len(problems))(*problems)
+    check(_lib.load().lbm3d_critical_pressure(arr, len(problems), ctypes.byref(o),
+                                              ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                              ctypes.c_void_p(st.cuda_stream), res),
+          "lbm3d_critical_pressure")
+    del ws
+    return [_result_dict(r) for r in res]
 
 
 # D3Q19 velocities in the library's numbering (include/lbm3d.h).

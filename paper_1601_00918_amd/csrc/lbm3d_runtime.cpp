@@ -28,7 +28,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMinStrip = 4;
-constexpr int kDefaultStrip = 16;
+constexpr int kDefaultStrip = 8;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }

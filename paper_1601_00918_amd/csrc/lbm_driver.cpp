@@ -3,7 +3,9 @@
 // documented in include/lbm.h.  The same state machine runs on the HIP engine
 // (lbm_critical_pressure: every problem in one batched launch per step,
 // finished probes restarted at once, finished problems dropped from the
-// launch) and on caller callbacks (lbm_cp_drive).
+// launch), on D3Q19 tube contexts (lbm3d_critical_pressure) and on caller
+// callbacks (lbm_cp_drive).
+#include "lbm3d.h"
 #include "lbm_ctx.h"
 
 #include <hip/hip_runtime.h>
@@ -300,6 +302,71 @@ struct HipEngine : CpEngine {
     }
 };
 
+// ---- engine over D3Q19 tube contexts (one per problem) -------------------------
+struct TubeEngine : CpEngine {
+    std::vector<lbm3d_ctx*> ctx;
+    std::vector<lbm3d_fluid> fluids;
+    ~TubeEngine() override
+    {
+        for (lbm3d_ctx* c : ctx)
+            lbm3d_destroy(c);
+    }
+    lbm_status begin_probe(int k, double g) override
+    {
+        lbm_status e = lbm3d_snapshot_restore(ctx[k]);
+        if (e != LBM_OK)
+            return e;
+        fluids[k].g[0] = g;
+        fluids[k].g[1] = fluids[k].g[2] = 0.0;
+        return lbm3d_set_fluid(ctx[k], &fluids[k]);
+    }
+    lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) override
+    {
+        for (size_t k = 0; k < ctx.size(); ++k)
+            if (active[k]) {
+                lbm_status e = lbm3d_step(ctx[k], steps);
+                if (e != LBM_OK)
+                    return e;
+            }
+        return LBM_OK;
+    }
+    lbm_status monitors(std::vector<lbm_monitor>& mon) override
+    {
+        for (size_t k = 0; k < ctx.size(); ++k) {
+            lbm_status e = lbm3d_monitors(ctx[k], &mon[k]);
+            if (e != LBM_OK)
+                return e;
+        }
+        return LBM_OK;
+    }
+};
+
+// The classification parameters of a tube problem in the planar problem's
+// terms: lambda, r0 as h0, a, nx; tau_w, sigma, rho_bar, bracket, budgets.
+lbm_cp_problem as_channel_problem(const lbm3d_cp_problem& q)
+{
+    lbm_cp_problem p{};
+    p.geom.kind = LBM_GEOM_CHANNEL;
+    p.geom.nx = q.geom.nx;
+    p.geom.ny = q.geom.ny;
+    p.geom.lambda = q.geom.lambda;
+    p.geom.h0 = q.geom.r0;
+    p.geom.a = q.geom.a;
+    p.fluid.tau[0] = q.fluid.tau[0];
+    p.fluid.tau[1] = q.fluid.tau[1];
+    p.fluid.G = q.fluid.G;
+    p.sigma = q.sigma;
+    p.rho_bar = q.rho_bar;
+    p.g_lo = q.g_lo;
+    p.g_hi = q.g_hi;
+    p.equil_steps = q.equil_steps;
+    p.max_steps = q.max_steps;
+    p.min_steps = q.min_steps;
+    return p;
+}
+
+constexpr size_t kTubeAlign = 256;
+
 // ---- engine over caller callbacks --------------------------------------------
 struct CallbackEngine : CpEngine {
     const lbm_cp_engine* cb = nullptr;
@@ -435,6 +502,79 @@ lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
         e = cp_run(eng, probs, n, o, results, steps0);
     lbm_destroy(eng.ctx);
     return e;
+}
+
+lbm_status lbm3d_cp_required_bytes(const lbm3d_cp_problem* probs, int32_t n, int32_t storage,
+                                   size_t* bytes)
+{
+    if (!probs || n < 1 || !bytes)
+        return fail(LBM_ERR_INVALID, "lbm3d_cp_required_bytes: bad argument");
+    size_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        size_t b = 0;
+        lbm_status e = lbm3d_required_bytes(&probs[k].geom, storage | LBM_OPT_SNAPSHOT, &b);
+        if (e != LBM_OK)
+            return e;
+        total += (b + kTubeAlign - 1) / kTubeAlign * kTubeAlign;
+    }
+    *bytes = total;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_critical_pressure(const lbm3d_cp_problem* probs, int32_t n,
+                                   const lbm_cp_options* opts, void* device_workspace,
+                                   size_t workspace_bytes, void* hip_stream,
+                                   lbm_cp_result* results)
+{
+    if (!probs || n < 1 || !results || !device_workspace)
+        return fail(LBM_ERR_INVALID, "lbm3d_critical_pressure: bad argument");
+    lbm_cp_options o;
+    if (opts)
+        o = *opts;
+    else
+        lbm_cp_default_options(&o);
+    lbm_status e = check_options(o);
+    if (e != LBM_OK)
+        return e;
+    std::vector<lbm_cp_problem> shadow(n);
+    for (int k = 0; k < n; ++k) {
+        if (probs[k].geom.kind != LBM3D_GEOM_TUBE)
+            return fail(LBM_ERR_INVALID, "problem %d: critical pressure needs a tube geometry", k);
+        shadow[k] = as_channel_problem(probs[k]);
+        if ((e = check_problem(shadow[k], k)) != LBM_OK)
+            return e;
+    }
+    size_t need = 0;
+    if ((e = lbm3d_cp_required_bytes(probs, n, o.storage, &need)) != LBM_OK)
+        return e;
+    if (workspace_bytes < need)
+        return fail(LBM_ERR_OOM, "lbm3d_critical_pressure: workspace of %zu bytes, %zu needed",
+                    workspace_bytes, need);
+    TubeEngine eng;
+    char* ws = (char*)device_workspace;
+    for (int k = 0; k < n; ++k) {
+        size_t b = 0;
+        lbm3d_required_bytes(&probs[k].geom, o.storage | LBM_OPT_SNAPSHOT, &b);
+        lbm3d_fluid f = probs[k].fluid;
+        f.g[0] = f.g[1] = f.g[2] = 0.0;
+        lbm3d_ctx* c = nullptr;
+        if ((e = lbm3d_init(&probs[k].geom, &f, &probs[k].init, o.storage | LBM_OPT_SNAPSHOT, ws,
+                            b, hip_stream, &c)) != LBM_OK)
+            return e;
+        eng.ctx.push_back(c);
+        eng.fluids.push_back(f);
+        ws += (b + kTubeAlign - 1) / kTubeAlign * kTubeAlign;
+    }
+    // Unforced equilibration, then the state every probe restarts from.
+    std::vector<int64_t> steps0(n, 0);
+    for (int k = 0; k < n; ++k) {
+        if ((e = lbm3d_step(eng.ctx[k], probs[k].equil_steps)) != LBM_OK)
+            return e;
+        if ((e = lbm3d_snapshot_save(eng.ctx[k])) != LBM_OK)
+            return e;
+        steps0[k] = probs[k].equil_steps;
+    }
+    return cp_run(eng, shadow.data(), n, o, results, steps0);
 }
 
 lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs, int32_t n,

@@ -139,3 +139,42 @@ def test_degenerate_and_oversized_inputs_are_rejected():
         binding.lbm_required_bytes([_geom(nx=1 << 16, ny=1 << 12, lam=16384.0, h0=1000.0,
                                           a=10.0)])
     assert e.value.status == 1
+
+
+def test_lbm3d_required_bytes_and_validation():
+    from paper_1601_00918_amd import binding3d as b3
+    g = b3.geom3_struct("tube", 96, 18, 18, lam=32.0, r0=6.0, a=2.0)
+    f32 = b3.lbm3d_required_bytes(g, "f32")
+    f16 = b3.lbm3d_required_bytes(g, "f16")
+    snap = b3.lbm3d_required_bytes(g, "f32", snapshot=True)
+    pops32 = 2 * 18 * 18 * 19 * 128 * 8    # two buffers, 19 planes of 128 FP32 pairs per row
+    pops16 = 2 * 18 * 18 * 20 * 128 * 4    # 20 planes (references included) of 4-byte pairs
+    assert f32 - f16 == pops32 - pops16
+    assert snap - f32 == pops32 // 2
+    with pytest.raises(_lib.LbmError) as e:
+        b3.lbm3d_required_bytes(b3.geom3_struct("tube", 2, 18, 18, lam=32.0, r0=6.0, a=2.0))
+    assert e.value.status == 1
+    with pytest.raises(_lib.LbmError) as e:   # one buffer would exceed 32-bit offsets
+        b3.lbm3d_required_bytes(b3.geom3_struct("box", 4096, 1024, 64))
+    assert e.value.status == 6
+    with pytest.raises(_lib.LbmError):
+        b3.lbm3d_required_bytes(b3.geom3_struct("tube", 96, 18, 18, lam=32.0, r0=-1.0, a=2.0))
+    n = ctypes.c_size_t()
+    assert _lib.load().lbm3d_required_bytes(ctypes.byref(g), 9, ctypes.byref(n)) == 6
+
+
+def test_lbm3d_critical_pressure_validates_on_the_host():
+    """Rejected before any device work (the workspace pointer is never used)."""
+    import synth
+    from paper_1601_00918_amd import binding3d as b3
+    box = b3.cp3_problem(synth.config_box3d(n=16, r=4.0), 1e-5, 1e-4, 0.195, 1.03, 10, 100)
+    tube = b3.cp3_problem(synth.config_tube(lam=32, r0=6.0, a=2.0), 1e-4, 1e-5, 0.195, 1.03,
+                          10, 100)
+    res = (_lib.LbmCpResult * 1)()
+    opts = binding.cp_options()
+    lib = _lib.load()
+    for prob, what in ((box, "tube geometry"), (tube, "bracket")):
+        arr = (_lib.Lbm3dCpProblem * 1)(prob)
+        st = lib.lbm3d_critical_pressure(arr, 1, ctypes.byref(opts), ctypes.c_void_p(1 << 20),
+                                         1 << 30, None, res)
+        assert st == 1 and what in lib.lbm_last_error().decode()
