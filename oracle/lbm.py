@@ -21,7 +21,7 @@ class OrcParams(ctypes.Structure):
         ("nx", ctypes.c_int32),
         ("ny", ctypes.c_int32),
         ("periodic_y", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reg_order", ctypes.c_int32),
         ("tau", ctypes.c_double * 2),
         ("G", ctypes.c_double),
         ("rho_s", ctypes.c_double * 2),
@@ -39,6 +39,7 @@ def _lib():
         pp = ctypes.POINTER(OrcParams)
         lib.orc_equilibrium.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         lib.orc_regularize.argtypes = [dp, dp, dp, dp]
+        lib.orc_regularize3.argtypes = [dp, dp, dp, dp]
         lib.orc_densities.argtypes = [pp, u8p, dp, dp]
         lib.orc_interaction_sum.argtypes = [pp, u8p, dp, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, dp, dp]
@@ -95,14 +96,26 @@ def regularize(f, feq):
     return out, pi
 
 
+def regularize3(f, feq):
+    """Eq. 6 with the third-order Hermite terms: returns (f' [9], a3 [2,2,2])."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    feq = np.ascontiguousarray(feq, dtype=np.float64)
+    out = np.zeros(9)
+    a3 = np.zeros(8)
+    _lib().orc_regularize3(_dp(f), _dp(feq), _dp(out), _dp(a3))
+    return out, a3.reshape(2, 2, 2)
+
+
 class Params:
-    """Physical and lattice parameters of one oracle lattice."""
+    """Physical and lattice parameters of one oracle lattice (reg_order: Hermite
+    order of the regularization, 2 or 3)."""
 
     def __init__(self, nx, ny, tau=(1.0, 1.0), G=0.0, rho_s=(0.0, 0.0), g=(0.0, 0.0),
-                 periodic_y=False):
+                 periodic_y=False, reg_order=2):
         self.c = OrcParams()
         self.c.nx, self.c.ny = int(nx), int(ny)
         self.c.periodic_y = 1 if periodic_y else 0
+        self.c.reg_order = int(reg_order)
         self.c.tau[0], self.c.tau[1] = float(tau[0]), float(tau[1])
         self.c.G = float(G)
         self.c.rho_s[0], self.c.rho_s[1] = float(rho_s[0]), float(rho_s[1])

@@ -28,6 +28,10 @@
  *
  * Geometry: x is always periodic.  y is periodic when periodic_y != 0; otherwise
  * a node outside 0 <= y < ny counts as solid.
+ *
+ * Regularization: second-order Hermite projection of the non-equilibrium part
+ * (Eq. 6, the default), or with reg_order = 3 also its third-order Hermite
+ * projection (orc_regularize3), the higher-order variant of the cited schemes.
  */
 #include <math.h>
 #include <stdint.h>
@@ -47,7 +51,7 @@ static const double T0 = 1.0 / 3.0;
 typedef struct {
     int32_t nx, ny;
     int32_t periodic_y;
-    int32_t reserved;
+    int32_t reg_order; /* Hermite order of the regularization: 2 (0 means 2) or 3 */
     double tau[2];   /* single-species relaxation times tau^o, tau^w */
     double G;        /* interaction strength of Eq. 8 (repulsion: G < 0) */
     double rho_s[2]; /* wall potentials rho_s^o, rho_s^w (Sec. 2, last paragraph) */
@@ -132,6 +136,51 @@ void orc_regularize(const double *f, const double *feq, double *fneq, double *pi
         pi_neq[1] = pxy;
         pi_neq[2] = pyy;
     }
+}
+
+/* ---- Eq. 6 with the third-order Hermite terms (regularization of the cited
+ * higher-order schemes): besides the second-order projection above, f - feq is
+ * projected on the third-order Hermite polynomials
+ *   H3_i,abc = c_a c_b c_c - T0 (c_a d_bc + c_b d_ac + c_c d_ab),
+ *   a3_abc = sum_i H3_i,abc (f_i - feq_i),
+ *   f'_i += w_i / (6 T0^3) * sum_abc H3_i,abc a3_abc   (all 8 index triples).
+ * a3_out (may be NULL) receives a3 as [a][b][c], 8 values.                   */
+void orc_regularize3(const double *f, const double *feq, double *fneq, double *a3_out)
+{
+    orc_regularize(f, feq, fneq, NULL);
+    double a3[2][2][2];
+    int c[Q][2];
+    for (int i = 0; i < Q; ++i) {
+        c[i][0] = CXI[i];
+        c[i][1] = CYI[i];
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int g = 0; g < 2; ++g) {
+                double sum = 0.0;
+                for (int i = 0; i < Q; ++i) {
+                    const double h = c[i][a] * c[i][b] * c[i][g]
+                                   - T0 * (c[i][a] * (b == g) + c[i][b] * (a == g) + c[i][g] * (a == b));
+                    sum += h * (f[i] - feq[i]);
+                }
+                a3[a][b][g] = sum;
+            }
+    for (int i = 0; i < Q; ++i) {
+        double contraction = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int g = 0; g < 2; ++g) {
+                    const double h = c[i][a] * c[i][b] * c[i][g]
+                                   - T0 * (c[i][a] * (b == g) + c[i][b] * (a == g) + c[i][g] * (a == b));
+                    contraction += h * a3[a][b][g];
+                }
+        fneq[i] += WEIGHT[i] / (6.0 * T0 * T0 * T0) * contraction;
+    }
+    if (a3_out)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int g = 0; g < 2; ++g)
+                    a3_out[(a * 2 + b) * 2 + g] = a3[a][b][g];
 }
 
 /* ---- per-node densities of both species (solid nodes: 0) ------------------ */
@@ -254,7 +303,10 @@ int orc_step(const orc_params *p, const uint8_t *mask, const double *f_in,
                  * flux minus that of its own local equilibrium, i.e. at its own
                  * velocity j^s / rho^s. */
                 orc_equilibrium(st.rho[s], st.jx[s] / st.rho[s], st.jy[s] / st.rho[s], feq_own);
-                orc_regularize(fl, feq_own, fneq, NULL);
+                if (p->reg_order == 3)
+                    orc_regularize3(fl, feq_own, fneq, NULL);
+                else
+                    orc_regularize(fl, feq_own, fneq, NULL);
                 for (int i = 0; i < Q; ++i)                      /* Eq. 3 */
                     fpost[i] = feq_shift[i] + (1.0 - 1.0 / tau_mix) * fneq[i];
                 /* Eq. 1, left side: stream; half-way bounce-back at solid links. */

@@ -5,7 +5,14 @@ bounce-back).  Test infrastructure."""
 import numpy as np
 CX = np.array([0,1,0,-1,0,1,-1,-1,1]); CY = np.array([0,0,1,0,-1,1,1,-1,-1])
 W = np.array([4/9]+[1/9]*4+[1/36]*4); OPP = np.array([0,3,4,1,2,7,8,5,6])
-def run(f, mask, tau, G, rho_s, g, steps, periodic_y, dt=np.float64):
+def _h3(i, T0):
+    """Third-order Hermite tensor of velocity i (2 x 2 x 2)."""
+    c = np.array([CX[i], CY[i]], dtype=np.float64); I = np.eye(2)
+    return (np.einsum('a,b,c->abc', c, c, c) - T0 * (np.einsum('a,bc->abc', c, I) +
+            np.einsum('b,ac->abc', c, I) + np.einsum('c,ab->abc', c, I)))
+def run(f, mask, tau, G, rho_s, g, steps, periodic_y, dt=np.float64, reg3=False):
+    """reg3: add the third-order Hermite projection of f - feq to the
+    regularized part (w_i / (6 T0^3) H3_i : a3)."""
     f = f.astype(dt); w = W.astype(dt); cx = CX.astype(dt); cy = CY.astype(dt)
     ny, nx = mask.shape
     fl = mask.astype(bool)
@@ -40,13 +47,18 @@ def run(f, mask, tau, G, rho_s, g, steps, periodic_y, dt=np.float64):
                 cu = cx[i]*vx+cy[i]*vy; usq = vx*vx+vy*vy
                 return rho[s]*w[i]*(1+3*cu+dt(4.5)*cu*cu-dt(1.5)*usq+dt(4.5)*cu*cu*cu-dt(4.5)*cu*usq)
             pxx = np.zeros_like(rt); pxy = np.zeros_like(rt); pyy = np.zeros_like(rt)
+            a3 = np.zeros((2, 2, 2) + rt.shape)
             for i in range(9):
                 rs = np.where(fl, rho[s], 1)
                 d = f[s,i]-feq(jx[s]/rs,jy[s]/rs,i)  # species' own equilibrium
                 pxx += cx[i]*cx[i]*d; pxy += cx[i]*cy[i]*d; pyy += cy[i]*cy[i]*d
+                if reg3:
+                    a3 += _h3(i, 1/3)[..., None, None] * d
             om = 1-1/taum
             for i in range(9):
                 fneq = w[i]*dt(4.5)*((cx[i]*cx[i]-T0)*pxx+2*cx[i]*cy[i]*pxy+(cy[i]*cy[i]-T0)*pyy)
+                if reg3:
+                    fneq = fneq + w[i] * dt(4.5) * np.einsum('abc,abcyx->yx', _h3(i, 1/3), a3)
                 fp = (feq(usx,usy,i) + om*fneq)*fl
                 # stream
                 dst = shifted(fp, -CX[i], -CY[i], 0)  # value arriving at x from x - c_i

@@ -273,3 +273,89 @@ def test_numpy_brute_force_agrees():
             assert bad == 0
         b = np_bruteforce.run(f, mask, cfg["tau"], cfg["G"], cfg["rho_s"], cfg["g"], 3, py)
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+
+
+# ---- third-order Hermite regularization (collision variant) -----------------
+def _h3_tensor(c, T0=1.0 / 3.0):
+    I = np.eye(2)
+    return (np.einsum('a,b,c->abc', c, c, c) - T0 * (np.einsum('a,bc->abc', c, I) +
+            np.einsum('b,ac->abc', c, I) + np.einsum('c,ab->abc', c, I)))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_third_order_regularizer_projection(seed):
+    """The third-order regularized part f' keeps the mass, momentum and second
+    moment of the second-order one, reproduces the third-order Hermite moments
+    of f - feq, is a projection (regularizing feq + f' returns f'), and on
+    D2Q9 the xxx and yyy coefficients vanish (c^3 = c, so H_xxx = 0)."""
+    rng = np.random.default_rng(100 + seed)
+    f = 0.05 + 0.05 * rng.random(9)
+    feq = orc.equilibrium(f.sum(), 0.05 * rng.standard_normal(), 0.05 * rng.standard_normal())
+    f3, a3 = orc.regularize3(f, feq)
+    f2, _ = orc.regularize(f, feq)
+    cx, cy, w, _ = orc.lattice()
+    C = np.stack([cx, cy], axis=1).astype(float)
+    d = f3 - f2
+    # rounding of values of order 1e-2
+    assert abs(d.sum()) < 1e-16 and np.abs(C.T @ d).max() < 1e-16
+    assert np.abs(np.einsum('ia,ib,i->ab', C, C, d)).max() < 1e-16
+    H = np.array([_h3_tensor(c) for c in C])
+    np.testing.assert_allclose(np.einsum('iabc,i->abc', H, f3),
+                               np.einsum("iabc,i->abc", H, f - feq), rtol=0, atol=1e-15)
+    assert a3[0, 0, 0] == 0.0 and a3[1, 1, 1] == 0.0
+    g3, _ = orc.regularize3(feq + f3, feq)
+    np.testing.assert_allclose(g3, f3, rtol=0, atol=1e-15)
+
+
+def test_third_order_worked_values():
+    """Closed form on D2Q9: only a_xxy and a_xyy survive; the additions are
+    -+a_xyy / 2 on the x axis, -+a_xxy / 2 on the y axis and
+    (s_y a_xxy + s_x a_xyy) / 4 on the diagonal (s_x, s_y) (w_i / (2 T0^3) times
+    the Hermite value, checked here by hand for a distribution whose only
+    non-equilibrium content is a unit xxy moment)."""
+    feq = orc.equilibrium(1.0, 0.0, 0.0)
+    # f - feq concentrated on the diagonals with s_y-odd, s_x-even weights:
+    # sum H_xxy d = sum_diag (2 s_y / 3) d = 1 with d = (3/8) s_y on each diagonal
+    d = np.zeros(9)
+    for i, (sx, sy) in enumerate(zip(*orc.lattice()[:2])):
+        if sx != 0 and sy != 0:
+            d[i] = 0.375 * sy
+    f3, a3 = orc.regularize3(feq + d, feq)
+    f2, _ = orc.regularize(feq + d, feq)
+    assert a3[0, 0, 1] == pytest.approx(1.0, abs=1e-15)
+    assert a3[0, 1, 1] == pytest.approx(0.0, abs=1e-15)
+    want = np.zeros(9)
+    for i, (sx, sy) in enumerate(zip(*orc.lattice()[:2])):
+        if sx == 0 and sy != 0:
+            want[i] = -0.5 * sy
+        elif sx != 0 and sy != 0:
+            want[i] = 0.25 * sy
+    np.testing.assert_allclose(f3 - f2, want, rtol=0, atol=1e-15)
+
+
+def test_third_order_step_matches_numpy_and_reduces_at_tau_one():
+    """The oracle step with reg_order = 3 agrees with the numpy transcription's
+    tensor form, and at tau_mix = 1 (omega = 0: the regularized part drops out)
+    it equals the second-order step bit for bit."""
+    from tests import np_bruteforce
+    cfg = synth.config_channel(lam=8, h0=2, a=1, theta=60.0, g=1e-4, tau=(0.7, 1.2))
+    mask = synth.mask_of(cfg)
+    f = synth.random_populations(cfg["nx"], cfg["ny"], mask, seed=12, amp=0.05)
+    p3 = orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"],
+                    g=cfg["g"], reg_order=3)
+    a = f
+    for _ in range(3):
+        a, bad = orc.step_once(p3, mask, a)
+        assert bad == 0
+    b = np_bruteforce.run(f, mask, cfg["tau"], cfg["G"], cfg["rho_s"], cfg["g"], 3, False,
+                          reg3=True)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+    a2, _ = orc.step_once(orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"],
+                                     rho_s=cfg["rho_s"], g=cfg["g"]), mask, f)
+    a3, _ = orc.step_once(p3, mask, f)
+    assert np.abs(a3 - a2).max() > 1e-9          # the variant does change the step
+    p2t = orc.Params(cfg["nx"], cfg["ny"], tau=(1.0, 1.0), G=cfg["G"], rho_s=cfg["rho_s"],
+                     g=cfg["g"])
+    p3t = orc.Params(cfg["nx"], cfg["ny"], tau=(1.0, 1.0), G=cfg["G"], rho_s=cfg["rho_s"],
+                     g=cfg["g"], reg_order=3)
+    assert np.array_equal(orc.step_once(p2t, mask, f)[0], orc.step_once(p3t, mask, f)[0])
