@@ -325,6 +325,8 @@ def main():
                          "BX,BY,STRIP for --workload tube3d")
     ap.add_argument("--solves", type=int, default=128,
                     help="problems per set for --workload solves")
+    ap.add_argument("--reg-order", type=int, default=2, choices=(2, 3),
+                    help="Hermite order of the regularization for the D2Q9 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -344,6 +346,9 @@ def main():
         print(json.dumps(bench_tube(args)), flush=True)
         return
     cfgs, desc = workload(args.workload)
+    if args.reg_order != 2:
+        cfgs = [dict(c, reg_order=args.reg_order) for c in cfgs]
+        desc += "; third-order Hermite regularization"
     nf = fluid_nodes(cfgs)
     sim = Simulation(cfgs, storage=args.storage)
     if args.tiling:
@@ -373,14 +378,16 @@ def main():
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nf
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
     traffic = (measured_traffic(args.storage)
-               if args.workload == "batch" and not args.tiling else None)
+               if args.workload == "batch" and not args.tiling and args.reg_order == 2
+               else None)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": desc, "instances": len(cfgs), "fluid_nodes": nf,
-                   "storage": args.storage, "tiling": list(sim.tiling()[:2])},
+                   "storage": args.storage, "tiling": list(sim.tiling()[:2]),
+                   "reg_order": args.reg_order},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # measured HBM bytes per launch over the same launch time

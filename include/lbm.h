@@ -82,6 +82,12 @@ typedef struct {
                         contributes to Eq. 8 for species o and w */
     double g[2];     /* homogeneous body acceleration (x, y); the force on
                         species a is rho^a g */
+    int32_t reg_order; /* Hermite order of the regularized non-equilibrium part
+                          (Eq. 6): 2 (or 0) projects f - f^eq on the second-order
+                          polynomials only; 3 adds the third-order projection
+                          (on D2Q9 its xxy and xyy coefficients), the
+                          higher-order variant of the schemes the paper cites */
+    int32_t reserved;
 } lbm_fluid;
 
 /* Initial densities; populations start at rest equilibrium f_i = w_i rho0. */

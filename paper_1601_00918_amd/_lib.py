@@ -54,7 +54,8 @@ class LbmGeom(ctypes.Structure):
 
 class LbmFluid(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double * 2), ("G", ctypes.c_double),
-                ("rho_s", ctypes.c_double * 2), ("g", ctypes.c_double * 2)]
+                ("rho_s", ctypes.c_double * 2), ("g", ctypes.c_double * 2),
+                ("reg_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class LbmInitFields(ctypes.Structure):

@@ -40,12 +40,13 @@ def geom_struct(kind, nx, ny, lam=0.0, h0=0.0, a=0.0, mask=None, _keep=None):
     return g
 
 
-def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0)):
+def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0), reg_order=2):
     f = LbmFluid()
     f.tau[0], f.tau[1] = float(tau[0]), float(tau[1])
     f.G = float(G)
     f.rho_s[0], f.rho_s[1] = float(rho_s[0]), float(rho_s[1])
     f.g[0], f.g[1] = float(g[0]), float(g[1])
+    f.reg_order = int(reg_order)
     return f
 
 
@@ -70,7 +71,8 @@ def structs_from_config(cfg, rho0=None, keep=None):
     explicit initial field."""
     geom = geom_struct(cfg["kind"], cfg["nx"], cfg["ny"], cfg.get("lam", 0.0),
                        cfg.get("h0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep)
-    fluid = fluid_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)), cfg.get("g", (0, 0)))
+    fluid = fluid_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)), cfg.get("g", (0, 0)),
+                         cfg.get("reg_order", 2))
     if rho0 is not None:
         init = init_struct("field", rho0=rho0, _keep=keep)
     else:

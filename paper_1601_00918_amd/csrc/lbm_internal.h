@@ -25,7 +25,7 @@ struct InstDev {
     float G36;          // G / 36: the D2Q9 weights of Eq. 8 are multiples of 1/36
     float rho_s[2];     // wall potentials
     float g[2];         // body acceleration
-    float pad1;
+    int32_t reg3;       // 1: third-order Hermite regularization
     double Gd;          // G in double (pressure export)
 };
 
@@ -62,11 +62,12 @@ enum Mode : int { kStep = 0, kStepMon = 1, kMonOnly = 2, kExport = 3 };
 constexpr int kMonWidth = 8;
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the launch
-// status.
+// status.  r3 selects the step kernels with the third-order regularization
+// branch (taken by instances whose reg3 is set).
 // The rounding sequence of the 16-bit formats is keyed by the step number
 // seed + (seed_dev ? *seed_dev : 0) (seed_dev lets a captured graph take the
 // step number from device memory; see launch_set_seed).
-hipError_t launch_step(int storage, int bx, int mode, const void* fin, void* fout,
+hipError_t launch_step(int storage, int bx, int mode, bool r3, const void* fin, void* fout,
                        const InstDev* insts, const Item* items, int item_base, int n_items,
                        const Col* cols, double* partial, double* stage, uint32_t seed,
                        const uint32_t* seed_dev, hipStream_t stream);

@@ -135,9 +135,12 @@ __device__ __forceinline__ float rho9(const float* f)
 
 struct Mom {
     float rho, jx, jy, pxx, pxy, pyy;
+    float mxxy, mxyy;  // third moments sum c_x^2 c_y f, sum c_x c_y^2 f
 };
 
-// Zeroth, first and second moments of the 9 populations of one species.
+// Zeroth, first and second moments of the 9 populations of one species, and
+// the two third moments the third-order regularization needs (unused, and
+// removed by the compiler, in the second-order kernels).
 __device__ __forceinline__ Mom moments9(const float* f)
 {
     Mom m;
@@ -151,6 +154,8 @@ __device__ __forceinline__ Mom moments9(const float* f)
     m.pxx = a13 + diag;
     m.pyy = a24 + diag;
     m.pxy = a57 - a68;
+    m.mxxy = d57 - d86;
+    m.mxyy = d57 + d86;
     return m;
 }
 
@@ -175,8 +180,9 @@ struct ColG {
 // momentum flux Pi^neq = Pi - rho T0 I - j j / rho, the second moment of
 // f - f^eq(rho, j / rho) in closed form (the species' own equilibrium); on
 // D2Q9 it takes five distinct values (rest, axis x, axis y, two diagonals).
+template <bool R3>
 __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy, float om,
-                                                float (&out)[9])
+                                                bool reg3, float (&out)[9])
 {
     const float rinv = __builtin_amdgcn_rcpf(m.rho);
     const float ax = m.jx * rinv, ay = m.jy * rinv;
@@ -209,6 +215,32 @@ __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy
     pair(vy, b1, g2, out[2], out[4]);
     pair(vx + vy, b5, g5, out[5], out[7]);
     pair(vy - vx, b5, g6, out[6], out[8]);
+    if constexpr (R3) {
+        if (reg3) {
+            // Third-order Hermite part: on D2Q9 only the xxy and xyy
+            // coefficients of f - f^eq(rho, j / rho) survive,
+            //   a_xxy = M_xxy - T0 j_y - j_x^2 j_y / rho^2,
+            //   a_xyy = M_xyy - T0 j_x - j_x j_y^2 / rho^2,
+            // and w_i / (6 T0^3) H3_i : a3 adds -+a_xyy / 2 on the x axis,
+            // -+a_xxy / 2 on the y axis and (s_y a_xxy + s_x a_xyy) / 4 on the
+            // diagonal (s_x, s_y); odd in c, so mass, momentum and the second
+            // moment are unchanged.
+            const float axxy = m.mxxy - (m.jy * (1.0f / 3.0f) + m.jy * ax * ax);
+            const float axyy = m.mxyy - (m.jx * (1.0f / 3.0f) + m.jx * ay * ay);
+            const float t1 = om * (-0.5f * axyy);
+            const float t2 = om * (-0.5f * axxy);
+            const float t5 = om * (0.25f * (axxy + axyy));
+            const float t6 = om * (0.25f * (axxy - axyy));
+            out[1] += t1;
+            out[3] -= t1;
+            out[2] += t2;
+            out[4] -= t2;
+            out[5] += t5;
+            out[7] -= t5;
+            out[6] += t6;
+            out[8] -= t6;
+        }
+    }
 }
 
 // Byte offsets (relative to the instance's first byte) of the 9 pulled
@@ -240,7 +272,7 @@ __device__ __forceinline__ uint32_t pull_offsets(const InstDev& P, const int (&r
     return bb;
 }
 
-template <int BX, int MODE, bool PY, typename T>
+template <int BX, int MODE, bool PY, typename T, bool R3>
 __device__ __forceinline__ void march(const void* __restrict__ fin, void* __restrict__ fout,
                                       const InstDev& P, const Item& it, int item_idx,
                                       const Col* __restrict__ cols, double* __restrict__ partial,
@@ -481,7 +513,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                 for (int s = 0; s < 2; ++s) {
                     const float vx = ux + G36 * sx[s] + P.g[0];
                     const float vy = uy + G36 * sy[s] + P.g[1];
-                    collide_species(prev[s], vx, vy, om, out[s]);
+                    collide_species<R3>(prev[s], vx, vy, om, P.reg3 != 0, out[s]);
                 }
                 // Streaming stores: the populations are read back only by the
                 // next step, long after they would have left L2.
@@ -557,7 +589,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
     }
 }
 
-template <int BX, int MODE, typename T>
+template <int BX, int MODE, typename T, bool R3>
 __global__ void __launch_bounds__(BX)
 step_kernel(const void* __restrict__ fin, void* __restrict__ fout,
             const InstDev* __restrict__ insts, const Item* __restrict__ items, int item_base,
@@ -572,11 +604,11 @@ step_kernel(const void* __restrict__ fin, void* __restrict__ fout,
     const Item it = items[item_idx];
     const InstDev P = insts[it.inst];
     if (P.periodic_y)
-        march<BX, MODE, true, T>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring, rref,
-                                 red);
+        march<BX, MODE, true, T, R3>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
+                                     rref, red);
     else
-        march<BX, MODE, false, T>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
-                                  rref, red);
+        march<BX, MODE, false, T, R3>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
+                                      rref, red);
 }
 
 __global__ void set_seed_kernel(uint32_t* seed_dev, uint32_t v)
@@ -694,54 +726,59 @@ __global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ in
     }
 }
 
+// r3: kernels with the third-order regularization branch (instances with
+// reg3 take it); only the colliding modes have such a variant.
 template <int BX, typename T>
-hipError_t launch_step_bx(int mode, const void* fin, void* fout, const InstDev* insts,
+hipError_t launch_step_bx(int mode, bool r3, const void* fin, void* fout, const InstDev* insts,
                           const Item* items, int item_base, int n_items, const Col* cols,
                           double* partial, double* stage, uint32_t seed,
                           const uint32_t* seed_dev, hipStream_t stream)
 {
     const dim3 grid(n_items), block(BX);
+#define LBM_LAUNCH(M, R)                                                                   \
+    step_kernel<BX, M, T, R><<<grid, block, 0, stream>>>(fin, fout, insts, items, item_base, \
+                                                         cols, partial, stage, seed, seed_dev)
     switch (mode) {
     case kStep:
-        step_kernel<BX, kStep, T><<<grid, block, 0, stream>>>(fin, fout, insts, items, item_base,
-                                                              cols, partial, stage, seed, seed_dev);
+        if (r3)
+            LBM_LAUNCH(kStep, true);
+        else
+            LBM_LAUNCH(kStep, false);
         break;
     case kStepMon:
-        step_kernel<BX, kStepMon, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                                 item_base, cols, partial, stage,
-                                                                 seed, seed_dev);
+        if (r3)
+            LBM_LAUNCH(kStepMon, true);
+        else
+            LBM_LAUNCH(kStepMon, false);
         break;
     case kMonOnly:
-        step_kernel<BX, kMonOnly, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                                 item_base, cols, partial, stage,
-                                                                 seed, seed_dev);
+        LBM_LAUNCH(kMonOnly, false);
         break;
     case kExport:
-        step_kernel<BX, kExport, T><<<grid, block, 0, stream>>>(fin, fout, insts, items,
-                                                                item_base, cols, partial, stage,
-                                                                seed, seed_dev);
+        LBM_LAUNCH(kExport, false);
         break;
     default:
         return hipErrorInvalidValue;
     }
+#undef LBM_LAUNCH
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_step_t(int bx, int mode, const void* fin, void* fout, const InstDev* insts,
+hipError_t launch_step_t(int bx, int mode, bool r3, const void* fin, void* fout, const InstDev* insts,
                          const Item* items, int item_base, int n_items, const Col* cols,
                          double* partial, double* stage, uint32_t seed, const uint32_t* seed_dev,
                          hipStream_t stream)
 {
     switch (bx) {
     case 64:
-        return launch_step_bx<64, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<64, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
                                      partial, stage, seed, seed_dev, stream);
     case 128:
-        return launch_step_bx<128, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<128, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
                                       partial, stage, seed, seed_dev, stream);
     case 256:
-        return launch_step_bx<256, T>(mode, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<256, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
                                       partial, stage, seed, seed_dev, stream);
     default:
         return hipErrorInvalidValue;
@@ -750,7 +787,7 @@ hipError_t launch_step_t(int bx, int mode, const void* fin, void* fout, const In
 
 }  // namespace
 
-hipError_t launch_step(int storage, int bx, int mode, const void* fin, void* fout,
+hipError_t launch_step(int storage, int bx, int mode, bool r3, const void* fin, void* fout,
                        const InstDev* insts, const Item* items, int item_base, int n_items,
                        const Col* cols, double* partial, double* stage, uint32_t seed,
                        const uint32_t* seed_dev, hipStream_t stream)
@@ -759,13 +796,13 @@ hipError_t launch_step(int storage, int bx, int mode, const void* fin, void* fou
         return hipSuccess;
     switch (storage) {
     case 0:
-        return launch_step_t<float>(bx, mode, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_t<float>(bx, mode, r3, fin, fout, insts, items, item_base, n_items, cols,
                                     partial, stage, seed, seed_dev, stream);
     case 1:
-        return launch_step_t<F16Tag>(bx, mode, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_t<F16Tag>(bx, mode, r3, fin, fout, insts, items, item_base, n_items, cols,
                                      partial, stage, seed, seed_dev, stream);
     case 2:
-        return launch_step_t<BF16Tag>(bx, mode, fin, fout, insts, items, item_base, n_items,
+        return launch_step_t<BF16Tag>(bx, mode, r3, fin, fout, insts, items, item_base, n_items,
                                       cols, partial, stage, seed, seed_dev, stream);
     default:
         return hipErrorInvalidValue;

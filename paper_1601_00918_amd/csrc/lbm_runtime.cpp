@@ -141,6 +141,8 @@ lbm_status check_fluid(const lbm_fluid& f)
     }
     if (!std::isfinite(f.G))
         return fail(LBM_ERR_INVALID, "G must be finite");
+    if (f.reg_order != 0 && f.reg_order != 2 && f.reg_order != 3)
+        return fail(LBM_ERR_INVALID, "reg_order = %d must be 2 or 3 (0: 2)", f.reg_order);
     return LBM_OK;
 }
 
@@ -229,7 +231,18 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
     d.rho_s[1] = (float)f.rho_s[1];
     d.g[0] = (float)f.g[0];
     d.g[1] = (float)f.g[1];
+    d.reg3 = f.reg_order == 3 ? 1 : 0;
     d.Gd = f.G;
+}
+
+// Whether any instance uses the third-order regularization (then the step
+// launches the kernels with that branch).
+bool any_reg3(const lbm_ctx* c)
+{
+    for (const InstDev& d : c->idv)
+        if (d.reg3)
+            return true;
+    return false;
 }
 
 constexpr int kBxClasses[3] = {256, 128, 64};
@@ -345,8 +358,9 @@ lbm_status sync_all(lbm_ctx* c)
 lbm_status run_range(lbm_ctx* c, int bx, int mode, int item_base, int n_items,
                      uint32_t seed = 0, const uint32_t* seed_dev = nullptr)
 {
-    hipError_t e = launch_step(c->storage, bx, mode, c->buf[c->cur], c->buf[c->cur ^ 1],
-                               c->inst_d, c->items_d, item_base, n_items, c->cols_d,
+    hipError_t e = launch_step(c->storage, bx, mode, any_reg3(c), c->buf[c->cur],
+                               c->buf[c->cur ^ 1], c->inst_d, c->items_d, item_base, n_items,
+                               c->cols_d,
                                c->partial_d, c->stage_d, seed, seed_dev, c->stream);
     if (e != hipSuccess)
         return fail(LBM_ERR_DEVICE, "step launch failed: %s", hipGetErrorString(e));
@@ -699,7 +713,10 @@ lbm_status lbm_set_fluid(lbm_ctx* c, int32_t inst, const lbm_fluid* fluid)
     lbm_status st = check_fluid(*fluid);
     if (st != LBM_OK)
         return st;
+    const bool r3_before = any_reg3(c);
     fill_inst_params(c->idv[inst], *fluid);
+    if (any_reg3(c) != r3_before)
+        c->graph_dirty = true;  // the captured launches name the other kernels
     HIP_TRY(hipMemcpyAsync(c->inst_d + inst, &c->idv[inst], sizeof(InstDev),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

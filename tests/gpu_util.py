@@ -10,7 +10,8 @@ def oracle_lattice(cfg, rho0=None, mask=None):
     mask = synth.mask_of(cfg) if mask is None else mask
     rho0 = synth.rho0_of(cfg, mask) if rho0 is None else rho0
     p = orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"],
-                   g=cfg["g"], periodic_y=(cfg["kind"] == "box"))
+                   g=cfg["g"], periodic_y=(cfg["kind"] == "box"),
+                   reg_order=cfg.get("reg_order", 2))
     return orc.Lattice(p, mask, rho0), mask, rho0
 
 

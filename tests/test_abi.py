@@ -83,6 +83,9 @@ def test_init_rejects_bad_fluid_and_init_on_host():
     with pytest.raises(_lib.LbmError) as e:
         _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], ok_init, ws_bytes=1024)
     assert e.value.status == 3
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7, reg_order=4)], ok_init)
+    assert e.value.status == 1 and "reg_order" in str(e.value)
 
 
 def test_mask_with_two_fluid_runs_in_a_column_is_unsupported():
