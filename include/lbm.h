@@ -322,7 +322,31 @@ typedef struct {
     int32_t autotune;       /* 1: run lbm_autotune (32 steps per trial) at the start of
                                the equilibration when every problem's equil_steps covers
                                its steps; default 0 */
+    int32_t protocol;       /* LBM_CP_BISECT (default) or LBM_CP_RAMP */
+    int32_t reserved;
+    double ramp_dg;         /* LBM_CP_RAMP: forcing increment per level (> 0) */
+    int64_t ramp_steps;     /* LBM_CP_RAMP: steps per level, a multiple of chunk_steps
+                               (default 40000) */
 } lbm_cp_options;
+
+/*
+ * Protocols.
+ * LBM_CP_BISECT: the bisection over independent probes described above.
+ * LBM_CP_RAMP: the continuation of Sec. 3.4.  After the unforced equilibration
+ *   the forcing starts at g_lo and is raised by ramp_dg every ramp_steps steps
+ *   (level k: g_k = g_lo + k ramp_dg) in one continuous run.  The slug's
+ *   displacement X is counted from the start of a level at which it is still
+ *   (|U| < still_frac U_ref at the end of the previous level; otherwise it keeps
+ *   counting across the level change); the slug is mobilised at level k when X
+ *   reaches move_frac * lambda (or the state becomes non-physical: also
+ *   LBM_CP_UNSTABLE).  Result: g_hi = g_crit = g_k, g_lo = g_{k-1} (0 and
+ *   LBM_CP_NOT_CONVERGED when the first level already moves the slug),
+ *   probes = levels run.  Past g_hi, or after max_probes levels, without
+ *   mobilisation: g_lo = the last level, g_crit = g_hi = the problem's g_hi,
+ *   flags LBM_CP_UNDECIDED | LBM_CP_NOT_CONVERGED.  The engine must support
+ *   set_forcing.
+ */
+enum { LBM_CP_BISECT = 0, LBM_CP_RAMP = 1 };
 
 enum {
     LBM_CP_UNDECIDED = 1,   /* a probe hit its step budget */
@@ -358,7 +382,7 @@ lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
                                  lbm_cp_result* results);
 
 /*
- * The same bisection and classification driven through caller callbacks (for
+ * The same protocols and classification driven through caller callbacks (for
  * other engines and for testing the driver itself).  The driver calls
  *   begin_probe(user, k, g)        restart problem k from its equilibrated state
  *                                   with body acceleration g;
@@ -373,6 +397,9 @@ typedef struct {
     int (*advance)(void* user, const uint8_t* active, int64_t steps);
     int (*monitors)(void* user, lbm_monitor* mon);
     void* user;
+    int (*set_forcing)(void* user, int32_t k, double g); /* change problem k's body
+                                   acceleration in place (LBM_CP_RAMP only; may be NULL
+                                   for bisection) */
 } lbm_cp_engine;
 
 lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs, int32_t n,

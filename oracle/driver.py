@@ -180,6 +180,81 @@ def solve(engine, problems, **rules):
     return out
 
 
+def ramp(engine, problems, ramp_dg, ramp_steps=40000, **rules):
+    """Continuation search (Sec. 3.4: the forcing is switched on after the
+    unforced equilibration and raised by a fixed increment at fixed intervals
+    while the slug's centre of oil mass is tracked).  One continuous run per
+    problem: level k has g_k = g_lo + k * ramp_dg for ramp_steps steps.  The
+    displacement X is counted from the start of a level at which the slug is
+    still (|U| < still_frac * U_ref with the level's g, measured at the end of
+    the previous level); when it is not still the count continues across the
+    level change.  Mobilised at level k once X >= move_frac * lam, or when the
+    state turns non-physical (UNSTABLE).  Result: g_hi = g_crit = g_k and
+    g_lo = g_{k-1} (0 and NOT_CONVERGED if k = 0); without mobilisation up to
+    g_hi or within max_probes levels: g_lo = the last level, g_crit = g_hi =
+    the problem's g_hi, UNDECIDED | NOT_CONVERGED.  probes counts the levels.
+    engine additionally needs set_forcing(k, g)."""
+    R = dict(DEFAULT_RULES)
+    R.update(rules)
+    n = len(problems)
+    mon = engine.monitors()
+    st = []
+    for k, p in enumerate(problems):
+        st.append(dict(level=0, g=p["g_lo"], t_level=0, X=0.0,
+                       prev=_centre(mon[k], p["nx"]), U=0.0, moved=False, flags=0, levels=1))
+        engine.begin_probe(k, p["g_lo"])
+    active = [True] * n
+    while any(active):
+        engine.advance(list(active), R["chunk_steps"])
+        mon = engine.monitors()
+        for k in range(n):
+            if not active[k]:
+                continue
+            p, s, m = problems[k], st[k], mon[k]
+            s["t_level"] += R["chunk_steps"]
+            finished = False
+            if m["bad_nodes"] > 0 or not np.isfinite(m["oil_cos"] + m["oil_sin"] + m["oil_flux"]):
+                s["flags"] |= UNSTABLE
+                s["moved"] = finished = True
+            else:
+                x = _centre(m, p["nx"])
+                s["X"] += _wrap(x - s["prev"], p["nx"])
+                s["prev"] = x
+                s["U"] = m["oil_flux"] / m["mass"][0] if m["mass"][0] > 0 else 0.0
+                if s["X"] >= R["move_frac"] * p["lam"]:
+                    s["moved"] = finished = True
+            if not finished and s["t_level"] >= ramp_steps:
+                nu_w = (p["tau_w"] - 0.5) / 3.0
+                if abs(s["U"]) < R["still_frac"] * s["g"] * p["h0"] ** 2 / (3.0 * nu_w):
+                    s["X"] = 0.0
+                g_next = p["g_lo"] + (s["level"] + 1) * ramp_dg
+                if g_next > p["g_hi"] * (1.0 + 1e-12) or s["levels"] >= R["max_probes"]:
+                    finished = True
+                else:
+                    s["level"] += 1
+                    s["levels"] += 1
+                    s["g"] = g_next
+                    s["t_level"] = 0
+                    engine.set_forcing(k, g_next)
+            if finished:
+                active[k] = False
+    out = []
+    for k, p in enumerate(problems):
+        s = st[k]
+        flags = s["flags"]
+        if s["moved"]:
+            hi = s["g"]
+            lo = p["g_lo"] + (s["level"] - 1) * ramp_dg if s["level"] > 0 else 0.0
+            if s["level"] == 0:
+                flags |= NOT_CONVERGED
+        else:
+            lo, hi = s["g"], p["g_hi"]
+            flags |= UNDECIDED | NOT_CONVERGED
+        out.append(dict(g_lo=lo, g_hi=hi, g_crit=hi, probes=s["levels"], flags=flags,
+                        bo_crit=p["rho_bar"] * hi * p["nx"] * (p["h0"] - p["a"]) / p["sigma"]))
+    return out
+
+
 class OracleEngine:
     """Oracle lattices as a critical-pressure engine: equilibrate without
     forcing, keep that state, and restart every probe from it."""
@@ -193,6 +268,9 @@ class OracleEngine:
 
     def begin_probe(self, k, g):
         self.lat[k].restore_state(self.snap[k])
+        self.lat[k].set_body_force(g)
+
+    def set_forcing(self, k, g):
         self.lat[k].set_body_force(g)
 
     def advance(self, active, steps):

@@ -10,6 +10,9 @@ device workspace and the stream.  Functions keep the ABI's names:
     lbm_cp_required_bytes, lbm_critical_pressure, lbm_cp_drive, lbm_destroy
 
 ``Simulation`` bundles a context with the torch workspace that backs it.
+The D3Q19 tube and box (include/lbm3d.h) are in ``binding3d`` (``Simulation3D``,
+``lbm3d_*``, ``lbm3d_critical_pressure``); the surrogate network's kernels
+(include/lbm_mlp.h) in ``mlp``.
 """
 from .binding import (Simulation, cp_options, cp_problem, fluid_struct, geom_struct,
                       init_struct, lbm_cp_drive, lbm_cp_required_bytes, lbm_critical_pressure,

@@ -38,6 +38,7 @@ INIT3_UNIFORM, INIT3_DROPLET, INIT3_SLUG = 0, 1, 3
 
 OPT_SNAPSHOT = 0x100
 CP_UNDECIDED, CP_UNSTABLE, CP_WIDENED, CP_NOT_CONVERGED = 1, 2, 4, 8
+CP_BISECT, CP_RAMP = 0, 1
 
 
 class LbmTuneReport(ctypes.Structure):
@@ -87,7 +88,9 @@ class LbmCpOptions(ctypes.Structure):
                 ("chunk_steps", ctypes.c_int32), ("still_chunks", ctypes.c_int32),
                 ("max_probes", ctypes.c_int32), ("verify_bracket", ctypes.c_int32),
                 ("min_steps", ctypes.c_int64), ("storage", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("protocol", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ramp_dg", ctypes.c_double),
+                ("ramp_steps", ctypes.c_int64)]
 
 
 class LbmCpResult(ctypes.Structure):
@@ -127,11 +130,12 @@ CP_BEGIN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctype
 CP_ADVANCE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
                               ctypes.c_int64)
 CP_MONITORS = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(LbmMonitor))
+CP_SET_FORCING = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double)
 
 
 class LbmCpEngine(ctypes.Structure):
     _fields_ = [("begin_probe", CP_BEGIN), ("advance", CP_ADVANCE), ("monitors", CP_MONITORS),
-                ("user", ctypes.c_void_p)]
+                ("user", ctypes.c_void_p), ("set_forcing", CP_SET_FORCING)]
 
 
 _LIB = None

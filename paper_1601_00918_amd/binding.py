@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (CP_ADVANCE, CP_BEGIN, CP_MONITORS, GEOM_BOX, GEOM_CHANNEL, GEOM_MASK,
+from ._lib import (CP_ADVANCE, CP_BEGIN, CP_MONITORS, CP_RAMP, CP_SET_FORCING, GEOM_BOX, GEOM_CHANNEL, GEOM_MASK,
                    INIT_DROPLET, INIT_FIELD, INIT_LAYERS, INIT_SLUG, INIT_UNIFORM, OPT_SNAPSHOT,
                    STORE_BF16, STORE_F16, STORE_F32, LbmCpEngine, LbmCpOptions, LbmCpProblem,
                    LbmCpResult, LbmFluid, LbmGeom, LbmInitFields, LbmMonitor, LbmTuneReport,
@@ -220,6 +220,8 @@ def cp_options(**overrides):
     for k, v in overrides.items():
         if k == "storage" and isinstance(v, str):
             v = _STORAGE[v]
+        if k == "protocol" and isinstance(v, str):
+            v = {"bisect": 0, "ramp": CP_RAMP}[v]
         setattr(o, k, v)
     return o
 
@@ -269,9 +271,10 @@ def lbm_critical_pressure(problems, opts=None, device="cuda", stream=None):
 
 
 def lbm_cp_drive(engine, problems, opts=None):
-    """Run the library's bisection driver on a Python engine object with methods
+    """Run the library's driver on a Python engine object with methods
     begin_probe(k, g), advance(active_list, steps), monitors() -> list of
-    monitor dicts (keys as returned by lbm_monitors)."""
+    monitor dicts (keys as returned by lbm_monitors), and, for the ramp
+    protocol, set_forcing(k, g)."""
     n = len(problems)
 
     def _begin(user, k, g):
@@ -299,7 +302,15 @@ def lbm_cp_drive(engine, problems, opts=None):
         except Exception:
             return 1
 
-    cb = LbmCpEngine(CP_BEGIN(_begin), CP_ADVANCE(_advance), CP_MONITORS(_monitors), None)
+    def _set_forcing(user, k, g):
+        try:
+            engine.set_forcing(int(k), float(g))
+            return 0
+        except Exception:
+            return 1
+
+    sf = CP_SET_FORCING(_set_forcing) if hasattr(engine, "set_forcing") else CP_SET_FORCING()
+    cb = LbmCpEngine(CP_BEGIN(_begin), CP_ADVANCE(_advance), CP_MONITORS(_monitors), None, sf)
     res = (LbmCpResult * n)()
     o = opts if opts is not None else cp_options()
     check(_lib.load().lbm_cp_drive(ctypes.byref(cb), _arr(problems, LbmCpProblem), n,

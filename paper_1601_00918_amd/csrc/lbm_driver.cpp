@@ -25,6 +25,7 @@ constexpr int kMaxWiden = 8;
 struct CpEngine {
     virtual ~CpEngine() {}
     virtual lbm_status begin_probe(int k, double g) = 0;
+    virtual lbm_status set_forcing(int k, double g) = 0;
     virtual lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) = 0;
     virtual lbm_status monitors(std::vector<lbm_monitor>& mon) = 0;
 };
@@ -80,6 +81,13 @@ lbm_status check_options(const lbm_cp_options& o)
         o.storage < LBM_STORE_F32 ||
         o.storage > LBM_STORE_BF16)
         return fail(LBM_ERR_INVALID, "invalid critical-pressure options");
+    if (o.protocol != LBM_CP_BISECT && o.protocol != LBM_CP_RAMP)
+        return fail(LBM_ERR_INVALID, "unknown critical-pressure protocol %d", o.protocol);
+    if (o.protocol == LBM_CP_RAMP &&
+        (!(o.ramp_dg > 0.0) || !std::isfinite(o.ramp_dg) || o.ramp_steps < o.chunk_steps ||
+         o.ramp_steps % o.chunk_steps != 0))
+        return fail(LBM_ERR_INVALID, "ramp needs ramp_dg > 0 and ramp_steps a positive "
+                                     "multiple of chunk_steps");
     return LBM_OK;
 }
 
@@ -271,6 +279,113 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
     return LBM_OK;
 }
 
+// Continuation (LBM_CP_RAMP): one run per problem, the forcing raised level
+// by level until the slug is mobilised (rules in include/lbm.h).
+lbm_status ramp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_cp_options& o,
+                    lbm_cp_result* res, const std::vector<int64_t>& steps0)
+{
+    struct Ramp {
+        int level = 0;
+        double g = 0.0;
+        int64_t level_steps = 0;
+        double X = 0.0, xc_prev = 0.0, U = 0.0;
+        bool moved = false;
+    };
+    std::vector<Ramp> st(n);
+    std::vector<lbm_monitor> mon(n);
+    lbm_status e = eng.monitors(mon);
+    if (e != LBM_OK)
+        return e;
+    for (int k = 0; k < n; ++k) {
+        std::memset(&res[k], 0, sizeof(lbm_cp_result));
+        res[k].steps = steps0[k];
+        res[k].probes = 1;
+        st[k].g = probs[k].g_lo;
+        st[k].xc_prev = centroid(mon[k], probs[k].geom.nx);
+        if ((e = eng.begin_probe(k, st[k].g)) != LBM_OK)
+            return e;
+    }
+    std::vector<uint8_t> active(n, 1);
+    int remaining = n;
+    while (remaining > 0) {
+        if ((e = eng.advance(active, o.chunk_steps)) != LBM_OK)
+            return e;
+        if ((e = eng.monitors(mon)) != LBM_OK)
+            return e;
+        for (int k = 0; k < n; ++k) {
+            if (!active[k])
+                continue;
+            const lbm_cp_problem& p = probs[k];
+            Ramp& s = st[k];
+            lbm_cp_result& r = res[k];
+            s.level_steps += o.chunk_steps;
+            r.steps += o.chunk_steps;
+            const lbm_monitor& m = mon[k];
+            bool done = false;
+            if (m.bad_nodes > 0.0 || !std::isfinite(m.oil_cos + m.oil_sin + m.oil_flux)) {
+                r.flags |= LBM_CP_UNSTABLE;
+                s.moved = done = true;
+            } else {
+                const double nx = p.geom.nx;
+                const double xc = centroid(m, nx);
+                s.X += wrap_half(xc - s.xc_prev, nx);
+                s.xc_prev = xc;
+                s.U = m.mass[0] > 0.0 ? m.oil_flux / m.mass[0] : 0.0;
+                if (s.X >= o.move_frac * p.geom.lambda)
+                    s.moved = done = true;
+            }
+            if (!done && s.level_steps >= o.ramp_steps) {
+                const double nu_w = (p.fluid.tau[1] - 0.5) / 3.0;
+                const double u_ref = s.g * p.geom.h0 * p.geom.h0 / (3.0 * nu_w);
+                if (std::fabs(s.U) < o.still_frac * u_ref)
+                    s.X = 0.0;  // settled: count the next level's displacement afresh
+                const double g_next = p.g_lo + (double)(s.level + 1) * o.ramp_dg;
+                if (g_next > p.g_hi * (1.0 + 1e-12) || r.probes >= o.max_probes) {
+                    done = true;
+                } else {
+                    ++s.level;
+                    ++r.probes;
+                    s.g = g_next;
+                    s.level_steps = 0;
+                    if ((e = eng.set_forcing(k, s.g)) != LBM_OK)
+                        return e;
+                }
+            }
+            if (done) {
+                active[k] = 0;
+                --remaining;
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        const lbm_cp_problem& p = probs[k];
+        const Ramp& s = st[k];
+        lbm_cp_result& r = res[k];
+        if (s.moved) {
+            r.g_hi = s.g;
+            r.g_lo = s.level > 0 ? p.g_lo + (double)(s.level - 1) * o.ramp_dg : 0.0;
+            if (s.level == 0)
+                r.flags |= LBM_CP_NOT_CONVERGED;
+        } else {
+            r.g_lo = s.g;
+            r.g_hi = p.g_hi;
+            r.flags |= LBM_CP_UNDECIDED | LBM_CP_NOT_CONVERGED;
+        }
+        r.g_crit = r.g_hi;
+        const double D = p.geom.h0 - p.geom.a;
+        r.bo_crit = p.rho_bar * r.g_crit * (double)p.geom.nx * D / p.sigma;
+    }
+    return LBM_OK;
+}
+
+lbm_status run_protocol(CpEngine& eng, const lbm_cp_problem* probs, int n,
+                        const lbm_cp_options& o, lbm_cp_result* res,
+                        const std::vector<int64_t>& steps0)
+{
+    return o.protocol == LBM_CP_RAMP ? ramp_run(eng, probs, n, o, res, steps0)
+                                     : cp_run(eng, probs, n, o, res, steps0);
+}
+
 // ---- engine over the library's own context -----------------------------------
 struct HipEngine : CpEngine {
     lbm_ctx* ctx = nullptr;
@@ -282,6 +397,12 @@ struct HipEngine : CpEngine {
         lbm_status e = lbm_snapshot_restore(ctx, k);
         if (e != LBM_OK)
             return e;
+        fluids[k].g[0] = g;
+        fluids[k].g[1] = 0.0;
+        return lbm_set_fluid(ctx, k, &fluids[k]);
+    }
+    lbm_status set_forcing(int k, double g) override
+    {
         fluids[k].g[0] = g;
         fluids[k].g[1] = 0.0;
         return lbm_set_fluid(ctx, k, &fluids[k]);
@@ -316,6 +437,12 @@ struct TubeEngine : CpEngine {
         lbm_status e = lbm3d_snapshot_restore(ctx[k]);
         if (e != LBM_OK)
             return e;
+        fluids[k].g[0] = g;
+        fluids[k].g[1] = fluids[k].g[2] = 0.0;
+        return lbm3d_set_fluid(ctx[k], &fluids[k]);
+    }
+    lbm_status set_forcing(int k, double g) override
+    {
         fluids[k].g[0] = g;
         fluids[k].g[1] = fluids[k].g[2] = 0.0;
         return lbm3d_set_fluid(ctx[k], &fluids[k]);
@@ -376,6 +503,14 @@ struct CallbackEngine : CpEngine {
                    ? LBM_OK
                    : fail(LBM_ERR_INVALID, "engine begin_probe(%d) failed", k);
     }
+    lbm_status set_forcing(int k, double g) override
+    {
+        if (!cb->set_forcing)
+            return fail(LBM_ERR_INVALID, "the ramp protocol needs the engine's set_forcing");
+        return cb->set_forcing(cb->user, k, g) == 0
+                   ? LBM_OK
+                   : fail(LBM_ERR_INVALID, "engine set_forcing(%d) failed", k);
+    }
     lbm_status advance(const std::vector<uint8_t>& active, int64_t steps) override
     {
         return cb->advance(cb->user, active.data(), steps) == 0
@@ -408,6 +543,9 @@ void lbm_cp_default_options(lbm_cp_options* o)
     o->max_probes = 60;
     o->verify_bracket = 0;
     o->min_steps = 20000;
+    o->protocol = LBM_CP_BISECT;
+    o->ramp_dg = 0.0;
+    o->ramp_steps = 40000;
 }
 
 lbm_status lbm_cp_required_bytes(const lbm_cp_problem* probs, int32_t n, size_t* bytes)
@@ -499,7 +637,7 @@ lbm_status lbm_critical_pressure(const lbm_cp_problem* probs, int32_t n,
     if (e == LBM_OK)
         e = lbm_snapshot_save(eng.ctx);
     if (e == LBM_OK)
-        e = cp_run(eng, probs, n, o, results, steps0);
+        e = run_protocol(eng, probs, n, o, results, steps0);
     lbm_destroy(eng.ctx);
     return e;
 }
@@ -574,7 +712,7 @@ lbm_status lbm3d_critical_pressure(const lbm3d_cp_problem* probs, int32_t n,
             return e;
         steps0[k] = probs[k].equil_steps;
     }
-    return cp_run(eng, shadow.data(), n, o, results, steps0);
+    return run_protocol(eng, shadow.data(), n, o, results, steps0);
 }
 
 lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs, int32_t n,
@@ -596,7 +734,9 @@ lbm_status lbm_cp_drive(const lbm_cp_engine* engine, const lbm_cp_problem* probs
             return e;
     CallbackEngine eng;
     eng.cb = engine;
-    return cp_run(eng, probs, n, o, results, std::vector<int64_t>(n, 0));
+    if (o.protocol == LBM_CP_RAMP && !engine->set_forcing)
+        return fail(LBM_ERR_INVALID, "lbm_cp_drive: the ramp protocol needs set_forcing");
+    return run_protocol(eng, probs, n, o, results, std::vector<int64_t>(n, 0));
 }
 
 }  // extern "C"

@@ -167,3 +167,78 @@ def test_lazy_bracket_check_matches_the_oracle_and_recovers_wrong_brackets():
     # inside bracket: plain bisection, no end probes, no widening
     assert lib[0]["flags"] == 0 and lib[0]["probes"] == math.ceil(math.log2(math.log(1.5) / 0.005))
     assert lib[1]["flags"] & binding._lib.CP_WIDENED and lib[2]["flags"] & binding._lib.CP_WIDENED
+
+
+class RampEngine(FakeEngine):
+    """FakeEngine with in-place forcing changes (the slug keeps its state)."""
+
+    def set_forcing(self, k, g):
+        self.state[k]["g"] = g
+
+
+def _ramp_problems(g_stars, levels=12):
+    cfgs, plain = [], []
+    for k, gs in enumerate(g_stars):
+        cfg = synth.config_channel(lam=64, theta=90.0)
+        lo, hi = 0.8 * gs, 0.8 * gs + levels * 0.04 * gs
+        cfgs.append(binding.cp_problem(cfg, lo, hi, sigma=0.161, rho_bar=1.03, equil_steps=0,
+                                       max_steps=200000))
+        plain.append(dict(nx=cfg["nx"], lam=cfg["lam"], h0=cfg["h0"], a=cfg["a"],
+                          tau_w=cfg["tau"][1], g_lo=lo, g_hi=hi, max_steps=200000,
+                          sigma=0.161, rho_bar=1.03))
+    return cfgs, plain
+
+
+def test_ramp_finds_the_first_level_above_the_threshold():
+    """Levels g_k = 0.8 g* + k 0.04 g*: the first level strictly above g* is
+    k = 6 (1.04 g*); the slug moves within that level, so the library reports
+    g_crit = g_6 and g_lo = g_5, and the oracle's implementation agrees."""
+    g_stars = [3.3e-5, 1.1e-6]
+    probs, plain = _ramp_problems(g_stars)
+    rules = dict(chunk_steps=1000)
+    for k, gs in enumerate(g_stars):
+        dg = 0.04 * gs
+        opts = binding.cp_options(protocol="ramp", ramp_dg=dg, ramp_steps=40000, **rules)
+        res = binding.lbm_cp_drive(RampEngine([plain[k]], [gs]), [probs[k]], opts)[0]
+        ref = odrv.ramp(RampEngine([plain[k]], [gs]), [plain[k]], dg, 40000, **rules)[0]
+        print(res, ref)
+        assert res["g_crit"] == pytest.approx(0.8 * gs + 6 * dg, rel=1e-12)
+        assert res["g_lo"] == pytest.approx(0.8 * gs + 5 * dg, rel=1e-12)
+        assert res["probes"] == 7 and res["flags"] == 0
+        for key in ("g_lo", "g_hi", "g_crit", "probes", "flags"):
+            assert res[key] == pytest.approx(ref[key], rel=1e-12), key
+
+
+def test_ramp_without_mobilisation_and_bad_options():
+    """A threshold above the ramp's top level: undecided, g_crit = g_hi.  The
+    ramp needs set_forcing, ramp_dg > 0 and ramp_steps a multiple of the chunk."""
+    g_stars = [3.3e-5]
+    probs, plain = _ramp_problems(g_stars, levels=3)
+    opts = binding.cp_options(protocol="ramp", ramp_dg=0.04 * g_stars[0], ramp_steps=20000)
+    res = binding.lbm_cp_drive(RampEngine(plain, g_stars), probs, opts)[0]
+    ref = odrv.ramp(RampEngine(plain, g_stars), plain, 0.04 * g_stars[0], 20000)[0]
+    assert res["flags"] == ref["flags"] == 1 | 8
+    assert res["g_crit"] == pytest.approx(plain[0]["g_hi"], rel=1e-12)
+    assert res["probes"] == ref["probes"] == 4
+    with pytest.raises(binding._lib.LbmError):
+        binding.lbm_cp_drive(FakeEngine(plain, g_stars), probs, opts)   # no set_forcing
+    with pytest.raises(binding._lib.LbmError):
+        binding.lbm_cp_drive(RampEngine(plain, g_stars), probs,
+                             binding.cp_options(protocol="ramp", ramp_dg=0.0))
+    with pytest.raises(binding._lib.LbmError):
+        binding.lbm_cp_drive(RampEngine(plain, g_stars), probs,
+                             binding.cp_options(protocol="ramp", ramp_dg=1e-6, ramp_steps=1500))
+
+
+def test_ramp_carries_the_displacement_of_a_moving_slug():
+    """A slug still creeping (never settles) at the end of a level keeps its
+    displacement across the level change; a settled one starts afresh."""
+    g_stars = [1e-4]
+    probs, plain = _ramp_problems(g_stars, levels=12)
+    dg = 0.04 * g_stars[0]
+    opts = binding.cp_options(protocol="ramp", ramp_dg=dg, ramp_steps=40000)
+    # creeper: U = 1e-4 below g*, 4 nodes per level; lambda / 2 = 32 nodes takes 8 levels
+    res = binding.lbm_cp_drive(RampEngine(plain, g_stars, creepers=[0]), probs, opts)[0]
+    ref = odrv.ramp(RampEngine(plain, g_stars, creepers=[0]), plain, dg, 40000)[0]
+    assert res["probes"] == ref["probes"] and res["g_crit"] == pytest.approx(ref["g_crit"])
+    assert res["g_crit"] <= 0.8 * g_stars[0] + 6 * dg + 1e-18

@@ -1,0 +1,144 @@
+"""The continuation (ramp) protocol of Sec. 3.4 on the GPU: the batched D2Q9
+engine against the oracle engine on the same levels, consistency with the
+bisection threshold, and the D3Q19 tube engine against the same driver on
+callbacks."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import driver as odrv
+from oracle import lbm as orc
+from paper_1601_00918_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 0.161
+RHO_BAR = 1.03
+
+
+def test_ramp_matches_oracle_and_brackets_the_bisection(gpu_available):
+    cfg = synth.config_channel(lam=64, theta=90.0)
+    rules = dict(chunk_steps=500, still_chunks=3, min_steps=5000)
+    equil = 4000
+    # the bisection threshold first (probes from rest)
+    bis = binding.lbm_critical_pressure(
+        [binding.cp_problem(cfg, 1e-5, 1.6e-4, SIGMA, RHO_BAR, equil, 30000)],
+        binding.cp_options(rel_tol=0.01, **rules))[0]
+    g_b = bis["g_crit"]
+    lo, dg, levels = 0.7 * g_b, 0.1 * g_b, 8
+    hi = lo + levels * dg
+    prob = binding.cp_problem(cfg, lo, hi, SIGMA, RHO_BAR, equil, 30000)
+    opts = binding.cp_options(protocol="ramp", ramp_dg=dg, ramp_steps=10000, **rules)
+    gpu = binding.lbm_critical_pressure([prob], opts)[0]
+    mask = synth.mask_of(cfg)
+    L = orc.Lattice(orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"],
+                               rho_s=cfg["rho_s"]), mask, synth.rho0_of(cfg, mask))
+    plain = dict(nx=cfg["nx"], lam=cfg["lam"], h0=cfg["h0"], a=cfg["a"], tau_w=cfg["tau"][1],
+                 g_lo=lo, g_hi=hi, max_steps=30000, sigma=SIGMA, rho_bar=RHO_BAR)
+    ref = odrv.ramp(odrv.OracleEngine([L], equil), [plain], dg, 10000, **rules)[0]
+    print("bisection", bis, "ramp gpu", gpu, "oracle", ref)
+    assert gpu["flags"] == 0 and ref["flags"] == 0
+    # same level, unless the threshold sits within rounding of a level
+    assert abs(round((gpu["g_crit"] - ref["g_crit"]) / dg)) <= 1
+    assert gpu["g_crit"] == pytest.approx(ref["g_crit"], rel=0.11)
+    # a ramp that lingers 10000 steps per level mobilises at or above the
+    # threshold of probes from rest, within one level and the protocols'
+    # different histories
+    assert 0.85 * g_b <= gpu["g_crit"] <= g_b + 2 * dg
+
+
+class _TubeRampEngine:
+    def __init__(self, cfg, equil):
+        from paper_1601_00918_amd.binding3d import Simulation3D
+        self.sim = Simulation3D(dict(cfg, g=(0.0, 0.0, 0.0)), snapshot=True)
+        self.sim.step(equil)
+        self.sim.snapshot_save()
+
+    def begin_probe(self, k, g):
+        self.sim.snapshot_restore()
+        self.sim.set_body_force(g)
+
+    def set_forcing(self, k, g):
+        self.sim.set_body_force(g)
+
+    def advance(self, active, steps):
+        if active[0]:
+            self.sim.step(steps)
+
+    def monitors(self):
+        return [self.sim.monitors()]
+
+
+def test_tube_ramp_equals_callback_driver(gpu_available):
+    from paper_1601_00918_amd import binding3d as b3
+    cfg = synth.config_tube(lam=32, r0=6.0, a=2.0, theta=120.0)
+    lo, dg, equil = 2.8e-4, 0.3e-4, 2000
+    rules = dict(chunk_steps=500, still_chunks=3)
+    opts = binding.cp_options(protocol="ramp", ramp_dg=dg, ramp_steps=5000, **rules)
+    native = b3.lbm3d_critical_pressure(
+        [b3.cp3_problem(cfg, lo, lo + 8 * dg, 0.195, RHO_BAR, equil, 20000)], opts)[0]
+    chan = dict(kind="channel", nx=cfg["nx"], ny=cfg["ny"], lam=cfg["lam"], h0=cfg["r0"],
+                a=cfg["a"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"], g=(0.0, 0.0),
+                init=dict(kind="slug", x0=cfg["init"]["x0"], length=cfg["init"]["length"]))
+    prob = binding.cp_problem(chan, lo, lo + 8 * dg, 0.195, RHO_BAR, equil, 20000)
+    cb = binding.lbm_cp_drive(_TubeRampEngine(cfg, equil), [prob], opts)[0]
+    print("native", native, "callbacks", cb)
+    for key in ("g_lo", "g_hi", "g_crit", "probes", "flags"):
+        assert native[key] == cb[key], key
+    assert native["flags"] & 8 == 0
+
+
+def test_paper_tube_ramp_four_initial_positions(gpu_available):
+    """The paper's tube at its D = 8 resolution (neck radius 8, widest 20,
+    lambda = 48, three periods, L = 144; Sec. 3.4), neutral wetting, tau = 1,
+    slugs of about 58 D^3 (the volume the paper targets) whose left edges are
+    a quarter wavelength apart: equilibrate 40,000 steps, then ramp the forcing
+    in steps of Delta Bo = 0.02 every 40,000 steps.  The slug volume is
+    measured after the equilibration with the 90 % rule (nodes whose oil
+    fraction exceeds 0.9) and the critical Bo compared with the quasi-static
+    axisymmetric Young-Laplace value for that volume.  The paper finds no
+    dependence on the initial position and agreement within 1.3 %.  Here the
+    ratio to the analytic value must not depend on the position (spread
+    <= 0.03) and must lie within 20 %: half-way bounce-back on the voxelised
+    wall and the interface, about 4 nodes wide, leave the effective meniscus
+    radii at a neck radius of 8 uncertain by about one node (12 % in
+    curvature)."""
+    from oracle import young_laplace as yl
+    from paper_1601_00918_amd import binding3d as b3
+    D, sig, rho_bar = 8, 0.195, 1.03
+    base = dict(lam=48, r0=14.0, a=6.0, nx=144, theta=90.0, tau=(1.0, 1.0))
+    col = synth.mask3_of(synth.config_tube(**base)).sum(axis=(0, 1))
+    cfgs = []
+    for j in range(4):
+        x0 = 4 + 12 * j
+        n = int(np.searchsorted(np.cumsum(np.roll(col, -x0)), 58.0 * D ** 3)) + 1
+        cfgs.append(synth.config_tube(slug_x0=x0, slug_len=n, **base))
+    L = cfgs[0]["nx"]
+    to_g = sig / (rho_bar * L * D)          # g per unit Bo
+    vols = []
+    for c in cfgs:
+        sim = b3.Simulation3D(c)
+        sim.step(40000)
+        rho = sim.moments()["rho"]
+        frac = rho[0] / np.maximum(rho[0] + rho[1], 1e-30)
+        vols.append(float((frac > 0.9).sum()) / D ** 3)
+    bo_yl = np.array([yl.bond_critical_tube(90.0, v) for v in vols])
+    # coarse location from probes at rest on the first position
+    bis = b3.lbm3d_critical_pressure(
+        [b3.cp3_problem(cfgs[0], 0.5 * to_g, 3.0 * to_g, sig, rho_bar, 40000, 160000,
+                        min_steps=20000)],
+        binding.cp_options(rel_tol=0.03, chunk_steps=1000, verify_bracket=1))[0]
+    start = max(0.02, round(bis["bo_crit"] / 0.02) * 0.02 - 0.1)
+    probs = [b3.cp3_problem(c, start * to_g, (start + 0.4) * to_g, sig, rho_bar, 40000,
+                            160000) for c in cfgs]
+    res = b3.lbm3d_critical_pressure(
+        probs, binding.cp_options(protocol="ramp", ramp_dg=0.02 * to_g, ramp_steps=40000,
+                                  chunk_steps=1000))
+    bos = np.array([r["bo_crit"] for r in res])
+    ratio = bos / bo_yl
+    print("slug lengths", [c["init"]["length"] for c in cfgs], "V/D^3", np.round(vols, 2),
+          "Bo_YL", np.round(bo_yl, 3), "bisection Bo", round(bis["bo_crit"], 3), "ramp Bo",
+          np.round(bos, 3), "ratio", np.round(ratio, 3), "flags", [r["flags"] for r in res])
+    assert all(r["flags"] & ~1 == 0 for r in res)
+    assert ratio.max() - ratio.min() <= 0.03
+    assert np.all(np.abs(ratio - 1) <= 0.2)
