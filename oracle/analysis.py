@@ -104,3 +104,32 @@ def contact_angle(R, y0, centre_on_oil_side):
     when the arc's centre lies on the oil side, else its supplement."""
     a = math.degrees(math.acos(min(1.0, y0 / R)))
     return a if centre_on_oil_side else 180.0 - a
+
+
+def meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8):
+    """Sec. 3.3 contact-angle detection on a slug between flat plates.
+
+    frac: oil fraction rho^o / (rho^o + rho^w), [ny][nx]; mask: fluid mask;
+    x_guess: approximate meniscus position; oil_left: True when oil is on the
+    meniscus's -x side.  Interfacial points: for every fluid row except the two
+    next to the walls, Eq. 12 fitted along x within x_guess +- window.  A circle
+    is fitted to the points and Eq. 14 applied with y0 the half width of the
+    channel (the walls sit half-way between the last fluid row and the solid
+    row beyond it).  Returns (theta through water in degrees, R, points)."""
+    frac = np.asarray(frac, dtype=float)
+    rows = np.nonzero(np.asarray(mask, dtype=bool).any(axis=1))[0]
+    lo, hi = rows.min(), rows.max()
+    y0 = 0.5 * (hi - lo + 1)
+    yc = 0.5 * (lo + hi)
+    xs, ys = [], []
+    nx = frac.shape[1]
+    x = np.arange(int(round(x_guess)) - window, int(round(x_guess)) + window + 1)
+    for yy in range(lo + 1, hi):
+        prof = frac[yy, np.mod(x, nx)]
+        c = fit_interface(x, prof, x_guess)
+        xs.append(c[2])
+        ys.append(yy - yc)
+    xc, ycc, R = circle_fit(xs, ys)
+    mean_x = float(np.mean(xs))
+    centre_on_oil = (xc < mean_x) if oil_left else (xc > mean_x)
+    return contact_angle(R, y0, centre_on_oil), R, (np.array(xs), np.array(ys))

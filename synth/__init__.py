@@ -167,6 +167,21 @@ def config_channel(lam=256, theta=90.0, tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug
                 init=dict(kind="slug", x0=slug_x0, length=slug_len))
 
 
+def config_plates(H=32, theta=90.0, tau=(1.0, 1.0), G=G_DEFAULT, nx=None, rho_s=None):
+    """An oil slug at rest between flat plates H nodes apart (a = 0 channel,
+    walls half-way between the outermost fluid rows and the solid rows):
+    nx = 4 H, slug of length nx / 2 from x = nx / 4.  rho_s overrides the
+    wall-potential map."""
+    nx = 4 * H if nx is None else nx
+    cfg = config_channel(lam=nx, theta=theta, tau=tau, G=G, h0=H // 2, a=0,
+                         slug_len=nx // 2, slug_x0=nx // 4)
+    cfg["nx"] = nx
+    cfg["name"] = "plates"
+    if rho_s is not None:
+        cfg["rho_s"] = tuple(rho_s)
+    return cfg
+
+
 def config_batch(n_inst=256, seed=1601, lams=(64, 128, 256, 512), G=G_DEFAULT,
                  sigma=0.05, rho_bar=1.03):
     """The batch of uneven channels: lam ~ U{lams}, h0 = lam/8, a = lam/16,

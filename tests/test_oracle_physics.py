@@ -173,3 +173,31 @@ def test_single_component_poiseuille():
     fluid = mask[:, 0] == 1
     err = np.abs(u[fluid] - want[fluid]).max() / want.max()
     assert err < 2e-3
+
+
+@pytest.mark.parametrize("theta", [30.0, 65.0, 90.5, 120.0, 155.0])
+def test_contact_angle_detection_recovers_a_known_arc(theta):
+    """Sec. 3.3 detection (Eq. 12 fits, circle fit, Eq. 14) on a synthetic
+    slug field whose front meniscus is an exact circular arc meeting the walls
+    at theta (through water), with a tanh profile of width 1.5 across it."""
+    from oracle import analysis as an
+    H, ny, nx = 32, 34, 160
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[1:ny - 1] = 1
+    y0 = H / 2.0
+    yc = 0.5 * (1 + ny - 2)
+    a = math.radians(theta)
+    # arc through the contact points (x_w, +-y0): centre on the oil side for
+    # theta < 90 (bulging into water), radius y0 / cos(theta)
+    xm = 100.0
+    if abs(math.cos(a)) < 1e-9:
+        xs_of = lambda y: np.full_like(y, xm)
+    else:
+        R = y0 / abs(math.cos(a))
+        sgn = 1.0 if theta < 90 else -1.0      # meniscus bulges into water (+x) for theta < 90
+        xcen = xm - sgn * R
+        xs_of = lambda y: xcen + sgn * np.sqrt(R * R - y * y)
+    Y, X = np.mgrid[0:ny, 0:nx].astype(float)
+    frac = 0.5 * (1.0 - np.tanh((X - xs_of(Y - yc)) / 1.5)) * mask
+    got, _, _ = an.meniscus_contact_angle(frac, mask, xm - 3.0, oil_left=True, window=12)
+    assert got == pytest.approx(theta, abs=0.3)
