@@ -26,6 +26,12 @@ class OrcParams(ctypes.Structure):
         ("G", ctypes.c_double),
         ("rho_s", ctypes.c_double * 2),
         ("g", ctypes.c_double * 2),
+        ("wall_interp", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("wall_yc", ctypes.c_double),
+        ("wall_h0", ctypes.c_double),
+        ("wall_a", ctypes.c_double),
+        ("wall_lam", ctypes.c_double),
     ]
 
 
@@ -40,6 +46,8 @@ def _lib():
         lib.orc_equilibrium.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         lib.orc_regularize.argtypes = [dp, dp, dp, dp]
         lib.orc_regularize3.argtypes = [dp, dp, dp, dp]
+        lib.orc_wall_fraction.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.orc_wall_fraction.restype = ctypes.c_double
         lib.orc_densities.argtypes = [pp, u8p, dp, dp]
         lib.orc_interaction_sum.argtypes = [pp, u8p, dp, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, dp, dp]
@@ -111,11 +119,17 @@ class Params:
     order of the regularization, 2 or 3)."""
 
     def __init__(self, nx, ny, tau=(1.0, 1.0), G=0.0, rho_s=(0.0, 0.0), g=(0.0, 0.0),
-                 periodic_y=False, reg_order=2):
+                 periodic_y=False, reg_order=2, wall=None):
+        """wall: None (half-way bounce-back) or (yc, h0, a, lam) of the channel
+        walls, placed at their sub-lattice positions by interpolated
+        bounce-back."""
         self.c = OrcParams()
         self.c.nx, self.c.ny = int(nx), int(ny)
         self.c.periodic_y = 1 if periodic_y else 0
         self.c.reg_order = int(reg_order)
+        if wall is not None:
+            self.c.wall_interp = 1
+            self.c.wall_yc, self.c.wall_h0, self.c.wall_a, self.c.wall_lam = (float(v) for v in wall)
         self.c.tau[0], self.c.tau[1] = float(tau[0]), float(tau[1])
         self.c.G = float(G)
         self.c.rho_s[0], self.c.rho_s[1] = float(rho_s[0]), float(rho_s[1])
@@ -131,6 +145,11 @@ class Params:
 
     def ref(self):
         return ctypes.byref(self.c)
+
+
+def wall_fraction(params, x, y, i):
+    """Fraction of the link from (x, y) along c_i at which it meets the wall."""
+    return _lib().orc_wall_fraction(params.ref(), int(x), int(y), int(i))
 
 
 def tau_mix(params, rho_o, rho_w):

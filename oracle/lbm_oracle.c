@@ -32,6 +32,11 @@
  * Regularization: second-order Hermite projection of the non-equilibrium part
  * (Eq. 6, the default), or with reg_order = 3 also its third-order Hermite
  * projection (orc_regularize3), the higher-order variant of the cited schemes.
+ *
+ * Walls: half-way bounce-back at solid links (default), or, with wall_interp,
+ * the analytic channel walls at their sub-lattice positions by linear
+ * interpolated bounce-back (orc_step_interp), which places the wall where the
+ * geometry puts it at the price of exact mass conservation.
  */
 #include <math.h>
 #include <stdint.h>
@@ -56,6 +61,12 @@ typedef struct {
     double G;        /* interaction strength of Eq. 8 (repulsion: G < 0) */
     double rho_s[2]; /* wall potentials rho_s^o, rho_s^w (Sec. 2, last paragraph) */
     double g[2];     /* homogeneous body acceleration (Sec. 3.4) */
+    /* Interpolated walls (wall_interp != 0): the channel walls
+     * y = wall_yc +- (wall_h0 + wall_a cos(2 pi x / wall_lam)) placed at their
+     * sub-lattice positions by linear interpolated bounce-back. */
+    int32_t wall_interp;
+    int32_t reserved2;
+    double wall_yc, wall_h0, wall_a, wall_lam;
 } orc_params;
 
 /* ---- lattice constants, exported so tests can check them ------------------ */
@@ -270,9 +281,119 @@ static void gather_node(const orc_params *p, const uint8_t *mask, const double *
  * f_in: state at time t; f_out: state at time t+1 (fully overwritten; solid
  * nodes are set to 0).  rho_work: [2][ny][nx] scratch.  Returns the number of
  * fluid nodes whose densities were not finite and positive (0 on success). */
+/* Fraction q in (0, 1] of the link from fluid node (x, y) along c_i at which
+ * it crosses the analytic channel wall (bisection on the segment). */
+double orc_wall_fraction(const orc_params *p, int x, int y, int i)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        const double t = 0.5 * (lo + hi);
+        const double X = x + t * CXI[i], Y = y + t * CYI[i];
+        const double h = p->wall_h0 + p->wall_a * cos(two_pi * X / p->wall_lam);
+        if (fabs(Y - p->wall_yc) < h)
+            lo = t;
+        else
+            hi = t;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Post-collision populations of both species at fluid node (x, y), Eq. 3. */
+static int collide_node(const orc_params *p, const uint8_t *mask, const double *f_in,
+                        const double *rho_work, int x, int y, double fpost[2][Q])
+{
+    const size_t n = (size_t)p->nx * p->ny;
+    const size_t k = (size_t)y * p->nx + x;
+    node_state st;
+    gather_node(p, mask, f_in, rho_work, x, y, &st);
+    const int bad = (!(st.rho[0] > 0.0) || !(st.rho[1] > 0.0) || !isfinite(st.rho[0] + st.rho[1]));
+    const double tau_mix = orc_tau_mix(p, st.rho[0], st.rho[1]);
+    for (int s = 0; s < 2; ++s) {
+        double fl[Q], feq_own[Q], feq_shift[Q], fneq[Q];
+        for (int i = 0; i < Q; ++i)
+            fl[i] = f_in[((size_t)s * Q + i) * n + k];
+        orc_equilibrium(st.rho[s], st.ux + st.fx[s] / st.rho[s], st.uy + st.fy[s] / st.rho[s],
+                        feq_shift);
+        orc_equilibrium(st.rho[s], st.jx[s] / st.rho[s], st.jy[s] / st.rho[s], feq_own);
+        if (p->reg_order == 3)
+            orc_regularize3(fl, feq_own, fneq, NULL);
+        else
+            orc_regularize(fl, feq_own, fneq, NULL);
+        for (int i = 0; i < Q; ++i)
+            fpost[s][i] = feq_shift[i] + (1.0 - 1.0 / tau_mix) * fneq[i];
+    }
+    return bad;
+}
+
+/* One step with interpolated walls: collide every node, then stream; a
+ * population f*_i(x) leaving towards a wall that the link crosses at fraction
+ * q returns as f_opp(i)(x) by the linear interpolated bounce-back of Bouzidi,
+ * Firdaouss and Lallemand (2001):
+ *   q <  1/2:  2q f*_i(x) + (1 - 2q) f*_i(x - c_i)     (x - c_i fluid; else f*_i(x))
+ *   q >= 1/2:  f*_i(x) / (2q) + (1 - 1/(2q)) f*_opp(i)(x)
+ * q = 1/2 is the half-way bounce-back of orc_step. */
+static int orc_step_interp(const orc_params *p, const uint8_t *mask, const double *f_in,
+                           double *f_out, double *rho_work)
+{
+    const int nx = p->nx, ny = p->ny;
+    const size_t n = (size_t)nx * ny;
+    int bad = 0;
+    orc_densities(p, mask, f_in, rho_work);
+    double *post = (double *)calloc(2 * Q * n, sizeof(double));
+    if (!post)
+        return -1;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t k = (size_t)y * nx + x;
+            if (!mask[k])
+                continue;
+            double fp[2][Q];
+            bad += collide_node(p, mask, f_in, rho_work, x, y, fp);
+            for (int s = 0; s < 2; ++s)
+                for (int i = 0; i < Q; ++i)
+                    post[((size_t)s * Q + i) * n + k] = fp[s][i];
+        }
+    memset(f_out, 0, sizeof(double) * 2 * Q * n);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t k = (size_t)y * nx + x;
+            if (!mask[k])
+                continue;
+            for (int s = 0; s < 2; ++s)
+                for (int i = 0; i < Q; ++i) {
+                    const double v = post[((size_t)s * Q + i) * n + k];
+                    const int xn = x + CXI[i], yn = y + CYI[i];
+                    if (node_is_fluid(p, mask, xn, yn)) {
+                        f_out[((size_t)s * Q + i) * n + node_index(p, xn, yn)] = v;
+                        continue;
+                    }
+                    const double q = orc_wall_fraction(p, x, y, i);
+                    double back;
+                    if (q < 0.5) {
+                        const int xb = x - CXI[i], yb = y - CYI[i];
+                        back = node_is_fluid(p, mask, xb, yb)
+                                   ? 2.0 * q * v + (1.0 - 2.0 * q) *
+                                         post[((size_t)s * Q + i) * n + node_index(p, xb, yb)]
+                                   : v;
+                    } else {
+                        back = v / (2.0 * q) +
+                               (1.0 - 1.0 / (2.0 * q)) * post[((size_t)s * Q + OPPOSITE[i]) * n + k];
+                    }
+                    f_out[((size_t)s * Q + OPPOSITE[i]) * n + k] = back;
+                }
+        }
+    free(post);
+    return bad;
+}
+
 int orc_step(const orc_params *p, const uint8_t *mask, const double *f_in,
              double *f_out, double *rho_work)
 {
+    if (p->wall_interp)
+        return orc_step_interp(p, mask, f_in, f_out, rho_work);
     const int nx = p->nx, ny = p->ny;
     const size_t n = (size_t)nx * ny;
     int bad = 0;

@@ -35,11 +35,12 @@ def channel_half_width(x, lam, h0, a):
     return h0 + a * np.cos(2.0 * np.pi * np.asarray(x, dtype=np.float64) / lam)
 
 
-def channel_mask(nx, ny, lam, h0, a):
-    """uint8 [ny, nx] fluid mask of a sinusoidal (a > 0) or flat (a = 0) channel."""
+def channel_mask(nx, ny, lam, h0, a, y_offset=0.0):
+    """uint8 [ny, nx] fluid mask of a sinusoidal (a > 0) or flat (a = 0) channel
+    whose centre line is y_c = (ny - 1) / 2 + y_offset."""
     x = np.arange(nx, dtype=np.float64)[None, :]
     y = np.arange(ny, dtype=np.float64)[:, None]
-    yc = 0.5 * (ny - 1)
+    yc = 0.5 * (ny - 1) + y_offset
     h = channel_half_width(x, lam, h0, a)
     return (np.abs(y - yc) < h).astype(np.uint8)
 
@@ -167,16 +168,23 @@ def config_channel(lam=256, theta=90.0, tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug
                 init=dict(kind="slug", x0=slug_x0, length=slug_len))
 
 
-def config_plates(H=32, theta=90.0, tau=(1.0, 1.0), G=G_DEFAULT, nx=None, rho_s=None):
+def config_plates(H=32, theta=90.0, tau=(1.0, 1.0), G=G_DEFAULT, nx=None, rho_s=None,
+                  offset=0.0):
     """An oil slug at rest between flat plates H nodes apart (a = 0 channel,
     walls half-way between the outermost fluid rows and the solid rows):
     nx = 4 H, slug of length nx / 2 from x = nx / 4.  rho_s overrides the
-    wall-potential map."""
+    wall-potential map.  offset (0 <= offset < 1) shifts both walls by that
+    fraction of a lattice spacing relative to the lattice (with interpolated
+    walls, wall_interp = 1; one more row of nodes is allotted)."""
     nx = 4 * H if nx is None else nx
     cfg = config_channel(lam=nx, theta=theta, tau=tau, G=G, h0=H // 2, a=0,
                          slug_len=nx // 2, slug_x0=nx // 4)
     cfg["nx"] = nx
     cfg["name"] = "plates"
+    if offset:
+        cfg["ny"] += 1
+        cfg["y_offset"] = float(offset) - 0.5
+        cfg["wall_interp"] = 1
     if rho_s is not None:
         cfg["rho_s"] = tuple(rho_s)
     return cfg
@@ -209,7 +217,8 @@ def config_batch(n_inst=256, seed=1601, lams=(64, 128, 256, 512), G=G_DEFAULT,
 def mask_of(cfg):
     if cfg["kind"] == "box":
         return box_mask(cfg["nx"], cfg["ny"])
-    return channel_mask(cfg["nx"], cfg["ny"], cfg["lam"], cfg["h0"], cfg["a"])
+    return channel_mask(cfg["nx"], cfg["ny"], cfg["lam"], cfg["h0"], cfg["a"],
+                        cfg.get("y_offset", 0.0))
 
 
 def rho0_of(cfg, mask=None):

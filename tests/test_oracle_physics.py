@@ -201,3 +201,83 @@ def test_contact_angle_detection_recovers_a_known_arc(theta):
     frac = 0.5 * (1.0 - np.tanh((X - xs_of(Y - yc)) / 1.5)) * mask
     got, _, _ = an.meniscus_contact_angle(frac, mask, xm - 3.0, oil_left=True, window=12)
     assert got == pytest.approx(theta, abs=0.3)
+
+
+# ---- interpolated (sub-lattice) walls ----------------------------------------
+def _plates_params(cfg, tau=(1.0, 1.0), G=None, g=(0.0, 0.0), interp=True):
+    yc = 0.5 * (cfg["ny"] - 1) + cfg.get("y_offset", 0.0)
+    return orc.Params(cfg["nx"], cfg["ny"], tau=tau, G=cfg["G"] if G is None else G,
+                      rho_s=cfg["rho_s"], g=g,
+                      wall=(yc, cfg["h0"], cfg["a"], cfg["lam"]) if interp else None)
+
+
+def test_wall_fraction_geometry():
+    """Link fractions against the walls' closed form (flat) and a direct root
+    of the sinusoidal wall along a diagonal link."""
+    from scipy.optimize import brentq
+    cfg = synth.config_plates(16, offset=0.2)
+    p = _plates_params(cfg)
+    # walls at y = 0.7 and 16.7; bottom fluid row 1, top 16
+    assert orc.wall_fraction(p, 5, 1, 4) == pytest.approx(0.3, abs=1e-12)
+    assert orc.wall_fraction(p, 5, 1, 7) == pytest.approx(0.3, abs=1e-12)
+    assert orc.wall_fraction(p, 5, 16, 2) == pytest.approx(0.7, abs=1e-12)
+    ch = synth.config_channel(lam=64, theta=90.0)
+    yc = 0.5 * (ch["ny"] - 1)
+    pc = orc.Params(ch["nx"], ch["ny"], wall=(yc, ch["h0"], ch["a"], ch["lam"]))
+    mask = synth.mask_of(ch)
+    x = 11
+    y = int(np.nonzero(mask[:, x])[0].min())      # lowest fluid row of column x
+    for i, (cx, cy) in ((4, (0, -1)), (7, (-1, -1)), (8, (1, -1))):
+        if mask[y + cy, (x + cx) % ch["nx"]]:
+            continue
+        def gap(t):
+            X, Y = x + t * cx, y + t * cy
+            return abs(Y - yc) - (ch["h0"] + ch["a"] * math.cos(2 * math.pi * X / ch["lam"]))
+        want = brentq(gap, 0.0, 1.0, xtol=1e-15)
+        assert orc.wall_fraction(pc, x, y, i) == pytest.approx(want, abs=1e-12)
+
+
+def test_interpolated_walls_at_half_way_equal_bounce_back():
+    """Walls exactly half-way between fluid and solid rows (q = 1/2): the
+    interpolated step is the half-way bounce-back step."""
+    cfg = synth.config_plates(16, theta=60.0)
+    mask = synth.mask_of(cfg)
+    f = synth.random_populations(cfg["nx"], cfg["ny"], mask, seed=21, amp=0.05)
+    a, _ = orc.step_once(_plates_params(cfg, interp=True), mask, f)
+    b, _ = orc.step_once(_plates_params(cfg, interp=False), mask, f)
+    assert np.abs(a - b).max() < 1e-15
+
+
+@pytest.mark.parametrize("offset", [0.2, 0.7])
+def test_interpolated_walls_give_poiseuille_at_the_true_walls(offset):
+    """A single fluid (G = 0, uniform densities) driven between plates whose
+    walls sit off the lattice: the steady profile is the parabola vanishing
+    at the analytic walls, u = g ((H/2)^2 - (y - y_c)^2) / (2 nu).  With
+    interpolated walls the error falls at second order in H (H = 8 -> 16:
+    about a quarter); half-way bounce-back on the same nodes, whose walls
+    snap to half-way positions, converges only at first order and is several
+    times further off."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3.0
+    errs = {}
+    for H in (8, 16):
+        g = 1e-5 * (8.0 / H) ** 2
+        cfg = synth.config_plates(H, offset=offset)
+        cfg["nx"] = 4
+        mask = synth.mask_of(cfg)
+        yc = 0.5 * (cfg["ny"] - 1) + cfg["y_offset"]
+        rho0 = np.stack([np.full(mask.shape, 0.5), np.full(mask.shape, 0.5)]) * mask
+        y = np.arange(cfg["ny"], dtype=float)
+        want = g * ((H / 2.0) ** 2 - (y - yc) ** 2) / (2.0 * nu)
+        rows = mask[:, 0].astype(bool)
+        for interp in (True, False):
+            p = _plates_params(cfg, tau=(tau, tau), G=0.0, g=(g, 0.0), interp=interp)
+            L = orc.Lattice(p, mask, rho0)
+            L.step(int(4000 * (H / 8) ** 2))
+            u = L.moments()["u"][0][:, 0]
+            errs[H, interp] = np.abs(u[rows] - want[rows]).max() / want.max()
+    print("offset", offset, {k: "%.2e" % v for k, v in errs.items()})
+    assert errs[8, True] < 0.03 and errs[16, True] < 0.006
+    assert 3.3 < errs[8, True] / errs[16, True] < 4.7          # second order
+    assert 1.5 < errs[8, False] / errs[16, False] < 2.5        # first order
+    assert errs[16, False] > 5 * errs[16, True]
