@@ -106,7 +106,7 @@ def contact_angle(R, y0, centre_on_oil_side):
     return a if centre_on_oil_side else 180.0 - a
 
 
-def meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8):
+def meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8, walls=None):
     """Sec. 3.3 contact-angle detection on a slug between flat plates.
 
     frac: oil fraction rho^o / (rho^o + rho^w), [ny][nx]; mask: fluid mask;
@@ -115,12 +115,16 @@ def meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8):
     next to the walls, Eq. 12 fitted along x within x_guess +- window.  A circle
     is fitted to the points and Eq. 14 applied with y0 the half width of the
     channel (the walls sit half-way between the last fluid row and the solid
-    row beyond it).  Returns (theta through water in degrees, R, points)."""
+    row beyond it; walls = (y_c, y0) gives the centre line and half width of
+    walls placed off the lattice instead).  Returns (theta through water in
+    degrees, R, points)."""
     frac = np.asarray(frac, dtype=float)
     rows = np.nonzero(np.asarray(mask, dtype=bool).any(axis=1))[0]
     lo, hi = rows.min(), rows.max()
     y0 = 0.5 * (hi - lo + 1)
     yc = 0.5 * (lo + hi)
+    if walls is not None:
+        yc, y0 = float(walls[0]), float(walls[1])
     xs, ys = [], []
     nx = frac.shape[1]
     x = np.arange(int(round(x_guess)) - window, int(round(x_guess)) + window + 1)

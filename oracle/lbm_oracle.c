@@ -282,10 +282,14 @@ static void gather_node(const orc_params *p, const uint8_t *mask, const double *
  * nodes are set to 0).  rho_work: [2][ny][nx] scratch.  Returns the number of
  * fluid nodes whose densities were not finite and positive (0 on success). */
 /* Fraction q in (0, 1] of the link from fluid node (x, y) along c_i at which
- * it crosses the analytic channel wall (bisection on the segment). */
+ * it crosses the analytic channel wall: in closed form for flat walls,
+ * otherwise by bisection on the segment, returning the upper end of the final
+ * interval. */
 double orc_wall_fraction(const orc_params *p, int x, int y, int i)
 {
     const double two_pi = 6.283185307179586476925286766559;
+    if (p->wall_a == 0.0) /* flat walls: links meet them along y only */
+        return (p->wall_h0 - fabs(y - p->wall_yc)) / fabs((double)CYI[i]);
     double lo = 0.0, hi = 1.0;
     for (int it = 0; it < 60; ++it) {
         const double t = 0.5 * (lo + hi);
@@ -296,7 +300,7 @@ double orc_wall_fraction(const orc_params *p, int x, int y, int i)
         else
             hi = t;
     }
-    return 0.5 * (lo + hi);
+    return hi; /* first point found outside: a wall exactly half-way gives 1/2 */
 }
 
 /* Post-collision populations of both species at fluid node (x, y), Eq. 3. */
@@ -332,7 +336,10 @@ static int collide_node(const orc_params *p, const uint8_t *mask, const double *
  * Firdaouss and Lallemand (2001):
  *   q <  1/2:  2q f*_i(x) + (1 - 2q) f*_i(x - c_i)     (x - c_i fluid; else f*_i(x))
  *   q >= 1/2:  f*_i(x) / (2q) + (1 - 1/(2q)) f*_opp(i)(x)
- * q = 1/2 is the half-way bounce-back of orc_step. */
+ * and the node's rest population gives back what the returned populations
+ * carry beyond f*_i(x), so each species' mass is kept exactly (with the wall
+ * potentials' force in the post-collision populations the plain scheme gains
+ * mass at every wall link).  q = 1/2 is the half-way bounce-back of orc_step. */
 static int orc_step_interp(const orc_params *p, const uint8_t *mask, const double *f_in,
                            double *f_out, double *rho_work)
 {
@@ -362,7 +369,8 @@ static int orc_step_interp(const orc_params *p, const uint8_t *mask, const doubl
             const size_t k = (size_t)y * nx + x;
             if (!mask[k])
                 continue;
-            for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < 2; ++s) {
+                double dm = 0.0; /* mass returned beyond half-way bounce-back */
                 for (int i = 0; i < Q; ++i) {
                     const double v = post[((size_t)s * Q + i) * n + k];
                     const int xn = x + CXI[i], yn = y + CYI[i];
@@ -383,7 +391,14 @@ static int orc_step_interp(const orc_params *p, const uint8_t *mask, const doubl
                                (1.0 - 1.0 / (2.0 * q)) * post[((size_t)s * Q + OPPOSITE[i]) * n + k];
                     }
                     f_out[((size_t)s * Q + OPPOSITE[i]) * n + k] = back;
+                    dm += back - v;
                 }
+                /* Keep each species' mass: the difference goes back through the
+                 * rest population, which carries no momentum (the rest
+                 * population streams to the node itself and is already stored). */
+                if (p->wall_interp == 1)
+                    f_out[((size_t)s * Q + 0) * n + k] -= dm;
+            }
         }
     free(post);
     return bad;
