@@ -57,7 +57,7 @@ typedef enum {
 typedef enum {
     LBM_GEOM_BOX = 0,     /* every node fluid, periodic in x and y */
     LBM_GEOM_CHANNEL = 1, /* walls at y = y_c +- (h0 + a cos(2 pi x / lambda)),
-                             y_c = (ny - 1) / 2; node fluid iff |y - y_c| < h(x)
+                             y_c = (ny - 1) / 2 + y_offset; node fluid iff |y - y_c| < h(x)
                              (a = 0: flat plates).  Rows outside 0..ny-1 are solid. */
     LBM_GEOM_MASK = 2     /* host mask [ny][nx], 1 = fluid; the fluid nodes of every
                              column must form one contiguous run of rows, and rows
@@ -67,9 +67,24 @@ typedef enum {
 typedef struct {
     int32_t kind;          /* lbm_geom_kind */
     int32_t nx, ny;        /* bounding box in nodes; 1 <= nx, ny <= 32768 */
-    int32_t reserved;
+    int32_t wall_interp;   /* LBM_GEOM_CHANNEL, FP32 storage: 1 places the walls at
+                              their sub-lattice positions by linear interpolated
+                              bounce-back (Bouzidi, Firdaouss and Lallemand 2001):
+                              a population leaving a fluid node towards a wall met
+                              at the fraction q of the link returns as
+                              2q f*_i(x) + (1 - 2q) f*_i(x - c_i) for q < 1/2 and
+                              f*_i(x) / (2q) + (1 - 1/(2q)) f*_opp(i)(x) otherwise,
+                              and the node's rest population gives back what that
+                              adds to the half-way value, so each species' mass is
+                              conserved (to rounding).  q is computed in FP64 at
+                              lbm_init (32 floats of workspace per column).  Walls
+                              steeper than one row per column are rejected
+                              (LBM_ERR_UNSUPPORTED).  0: half-way bounce-back */
     double lambda, h0, a;  /* LBM_GEOM_CHANNEL only */
     const uint8_t* mask;   /* LBM_GEOM_MASK only, [ny][nx], copied */
+    double y_offset;       /* LBM_GEOM_CHANNEL: centre line at y_c = (ny - 1) / 2 +
+                              y_offset (|y_offset| <= 1), to place walls off the
+                              lattice */
 } lbm_geom;
 
 /* Fluid parameters of one instance. */

@@ -49,8 +49,9 @@ class LbmTuneReport(ctypes.Structure):
 
 class LbmGeom(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("lam", ctypes.c_double), ("h0", ctypes.c_double),
-                ("a", ctypes.c_double), ("mask", ctypes.POINTER(ctypes.c_uint8))]
+                ("wall_interp", ctypes.c_int32), ("lam", ctypes.c_double),
+                ("h0", ctypes.c_double), ("a", ctypes.c_double),
+                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("y_offset", ctypes.c_double)]
 
 
 class LbmFluid(ctypes.Structure):

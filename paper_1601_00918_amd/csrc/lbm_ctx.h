@@ -26,7 +26,7 @@ struct InstHost {
 struct Layout {
     size_t buf_bytes;  // one population buffer
     size_t off_buf[2], off_snap, off_inst, off_items, off_cols, off_partial, off_mon,
-        off_first, off_count, off_stage, off_seed, total;
+        off_first, off_count, off_stage, off_seed, off_wq, total;
     int64_t n_items_max;
     int64_t max_nodes;
 };

@@ -27,7 +27,23 @@ struct InstDev {
     float g[2];         // body acceleration
     int32_t reg3;       // 1: third-order Hermite regularization
     double Gd;          // G in double (pressure export)
+    // Interpolated walls (channel, FP32 storage): the wall fraction q of every
+    // wall link, [nx][kWallSlots][8] (see wall_slot), or null for half-way
+    // bounce-back.
+    const float* wq;
 };
+
+// Rows of a column whose nodes may have wall links, when neighbouring fluid
+// runs differ by at most one row at each end: lo, lo + 1, hi - 1 and hi.  A
+// node's slot is y - lo if that is below 2, else 3 - (hi - y) if hi - y is
+// below 2, else it has none (-1).  Entry (x, slot, j - 1) of the wall table
+// is the fraction of the link from the node along -c_j (pulled direction j)
+// at which it meets the wall.
+constexpr int kWallSlots = 4;
+__host__ __device__ inline int wall_slot(int y, int lo, int hi)
+{
+    return y - lo < 2 ? y - lo : (hi - y < 2 ? 3 - (hi - y) : -1);
+}
 
 // A work item: one workgroup advances the columns x0..x0+BX-1 of instance
 // inst over rows y0..y1-1 marching up (y0 < y1), or over rows y0 down to
@@ -62,12 +78,12 @@ enum Mode : int { kStep = 0, kStepMon = 1, kMonOnly = 2, kExport = 3 };
 constexpr int kMonWidth = 8;
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the launch
-// status.  r3 selects the step kernels with the third-order regularization
-// branch (taken by instances whose reg3 is set).
+// status.  ext selects the extended step kernels, with the branches of the
+// optional features (taken by instances with reg3 set or a wall table).
 // The rounding sequence of the 16-bit formats is keyed by the step number
 // seed + (seed_dev ? *seed_dev : 0) (seed_dev lets a captured graph take the
 // step number from device memory; see launch_set_seed).
-hipError_t launch_step(int storage, int bx, int mode, bool r3, const void* fin, void* fout,
+hipError_t launch_step(int storage, int bx, int mode, bool ext, const void* fin, void* fout,
                        const InstDev* insts, const Item* items, int item_base, int n_items,
                        const Col* cols, double* partial, double* stage, uint32_t seed,
                        const uint32_t* seed_dev, hipStream_t stream);

@@ -133,6 +133,29 @@ __device__ __forceinline__ float rho9(const float* f)
     return ((f[0] + a13) + a24) + (a57 + a68);
 }
 
+// Interpolated walls (FP32 storage, instances with a wall table): the wall
+// fraction q of the link from node (x, y) along -c_j comes from the table the
+// runtime computes in FP64 (a wall exactly half-way gives q = 1/2, and the
+// blend below is then the half-way value itself); the linear interpolated
+// bounce-back of Bouzidi, Firdaouss and Lallemand (2001) for the population
+// pulled in direction j, given its half-way value f*_opp(j)(x) and
+//   q <  1/2: f*_opp(j)(x + c_j) (the half-way value again if that node is solid),
+//   q >= 1/2: f*_j(x).
+// What the blends add to the half-way values, summed over j = 1..8 in order,
+// is taken from the node's rest population, so each species keeps its mass.
+// Owner and halo lanes use these same functions and the same summation order,
+// so a wall node's density is bitwise the same whichever workgroup computes it.
+__device__ __forceinline__ float ibb_q(const InstDev& P, int x, int y, const Col& c, int j)
+{
+    return P.wq[(x * kWallSlots + wall_slot(y, c.lo, c.hi)) * 8 + (j - 1)];
+}
+
+__device__ __forceinline__ float ibb_blend(float q, float half_way, float extra)
+{
+    return q < 0.5f ? (2.0f * q) * half_way + (1.0f - 2.0f * q) * extra
+                    : half_way * (0.5f / q) + (1.0f - 0.5f / q) * extra;
+}
+
 struct Mom {
     float rho, jx, jy, pxx, pxy, pyy;
     float mxxy, mxyy;  // third moments sum c_x^2 c_y f, sum c_x c_y^2 f
@@ -272,7 +295,7 @@ __device__ __forceinline__ uint32_t pull_offsets(const InstDev& P, const int (&r
     return bb;
 }
 
-template <int BX, int MODE, bool PY, typename T, bool R3>
+template <int BX, int MODE, bool PY, typename T, bool EXT>
 __device__ __forceinline__ void march(const void* __restrict__ fin, void* __restrict__ fout,
                                       const InstDev& P, const Item& it, int item_idx,
                                       const Col* __restrict__ cols, double* __restrict__ partial,
@@ -312,10 +335,12 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
     const int hd = hj < 9 ? hj : 0;
     const int hcx = dir_cx(hd), hcy = dir_cy(hd), hopp = dir_opp(hd);
     const int hsx = hcx == 1 ? hxm : (hcx == -1 ? hxp : hx);
-    Col hgc{0, 0}, hgs{0, 0};
+    Col hgc{0, 0}, hgs{0, 0}, hge{0, 0};  // halo column, its source column, the one beyond
     if (!PY && hgrp) {
         hgc = cols[P.col_off + hx];
         hgs = cols[P.col_off + hsx];
+        if (EXT)
+            hge = cols[P.col_off + (hcx == 1 ? hxp : (hcx == -1 ? hxm : hx))];
     }
     // Reference-density lanes of wave 0 (16-bit formats): lanes 16 side + 9
     // and + 10 load the reference pairs of the two columns beyond each side
@@ -419,6 +444,41 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 S::unpack(rawp[i], raw[i], raw[9 + i]);
+            if constexpr (EXT && !S::kRef && !PY) {
+                if (P.wq && bb_next) {
+                    float dmo = 0.0f, dmw = 0.0f;  // added beyond half-way bounce-back
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        if (!((bb_next >> i) & 1u))
+                            continue;
+                        const int cx = kCx[i], cy = kCy[i];
+                        const float q = ibb_q(P, x, rr, g.c, i);
+                        uint32_t o_extra;
+                        bool use = true;
+                        if (q < 0.5f) {
+                            const Col ce = cx == 1 ? g.p : (cx == -1 ? g.m : g.c);
+                            const int ye = rr + cy;
+                            use = (ye >= ce.lo) & (ye <= ce.hi);
+                            const int xe = cx == 1 ? xp : (cx == -1 ? xm : x);
+                            o_extra = PB * ((uint32_t)(kOpp[i] * P.pitch) +
+                                            (uint32_t)(ye * RS + xe));
+                        } else {
+                            o_extra = PB * ((uint32_t)(i * P.pitch) + (uint32_t)(rr * RS + x));
+                        }
+                        float eo = raw[i], ew = raw[9 + i];
+                        if (use)
+                            S::unpack(S::load(base + o_extra), eo, ew);
+                        const float bo = ibb_blend(q, raw[i], eo);
+                        const float bw = ibb_blend(q, raw[9 + i], ew);
+                        dmo += bo - raw[i];
+                        dmw += bw - raw[9 + i];
+                        raw[i] = bo;
+                        raw[9 + i] = bw;
+                    }
+                    raw[0] -= dmo;
+                    raw[9] -= dmw;
+                }
+            }
             if (S::kRef) {
                 const uint32_t bbm = bb_next;
 #pragma unroll
@@ -446,8 +506,34 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         }
         if (tid < 64) {
             float v0 = 0.0f, v1 = 0.0f;
+            float e0 = 0.0f, e1 = 0.0f;  // interpolated walls: added beyond half-way
             if (hlane && hfl) {
                 S::unpack(hrawp, v0, v1);
+                if constexpr (EXT && !S::kRef && !PY) {
+                    if (P.wq && hbb_next) {
+                        const float q = ibb_q(P, hx, rr, hgc, hd);
+                        uint32_t o_extra;
+                        bool use = true;
+                        if (q < 0.5f) {
+                            const int ye = rr + hcy;
+                            use = (ye >= hge.lo) & (ye <= hge.hi);
+                            const int xe = hcx == 1 ? hxp : (hcx == -1 ? hxm : hx);
+                            o_extra = PB * ((uint32_t)(hopp * P.pitch) +
+                                            (uint32_t)(ye * RS + xe));
+                        } else {
+                            o_extra = PB * ((uint32_t)(hd * P.pitch) + (uint32_t)(rr * RS + hx));
+                        }
+                        float eo = v0, ew = v1;
+                        if (use)
+                            S::unpack(S::load(base + o_extra), eo, ew);
+                        const float b0 = ibb_blend(q, v0, eo);
+                        const float b1 = ibb_blend(q, v1, ew);
+                        e0 = b0 - v0;
+                        e1 = b1 - v1;
+                        v0 = b0;
+                        v1 = b1;
+                    }
+                }
                 if (S::kRef) {
                     const int ch = hside ? wdt + 2 : 1;
                     const int sl = hbb_next ? (r & 3) : ((r - hcy) & 3);
@@ -463,6 +549,18 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
             for (int j = 0; j < 9; ++j) {
                 q0[j] = __shfl(v0, (tid & ~15) + j, 64);
                 q1[j] = __shfl(v1, (tid & ~15) + j, 64);
+            }
+            if constexpr (EXT && !S::kRef && !PY) {
+                if (P.wq) {
+                    float dm0 = 0.0f, dm1 = 0.0f;
+#pragma unroll
+                    for (int j = 1; j < 9; ++j) {
+                        dm0 += __shfl(e0, (tid & ~15) + j, 64);
+                        dm1 += __shfl(e1, (tid & ~15) + j, 64);
+                    }
+                    q0[0] -= dm0;
+                    q1[0] -= dm1;
+                }
             }
             const float rh0 = rho9(q0), rh1 = rho9(q1);
             if (hgrp && hj == 0) {
@@ -513,7 +611,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                 for (int s = 0; s < 2; ++s) {
                     const float vx = ux + G36 * sx[s] + P.g[0];
                     const float vy = uy + G36 * sy[s] + P.g[1];
-                    collide_species<R3>(prev[s], vx, vy, om, P.reg3 != 0, out[s]);
+                    collide_species<EXT>(prev[s], vx, vy, om, P.reg3 != 0, out[s]);
                 }
                 // Streaming stores: the populations are read back only by the
                 // next step, long after they would have left L2.
@@ -589,7 +687,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
     }
 }
 
-template <int BX, int MODE, typename T, bool R3>
+template <int BX, int MODE, typename T, bool EXT>
 __global__ void __launch_bounds__(BX)
 step_kernel(const void* __restrict__ fin, void* __restrict__ fout,
             const InstDev* __restrict__ insts, const Item* __restrict__ items, int item_base,
@@ -604,10 +702,10 @@ step_kernel(const void* __restrict__ fin, void* __restrict__ fout,
     const Item it = items[item_idx];
     const InstDev P = insts[it.inst];
     if (P.periodic_y)
-        march<BX, MODE, true, T, R3>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
+        march<BX, MODE, true, T, EXT>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
                                      rref, red);
     else
-        march<BX, MODE, false, T, R3>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
+        march<BX, MODE, false, T, EXT>(fin, fout, P, it, item_idx, cols, partial, stage, sd, ring,
                                       rref, red);
 }
 
@@ -715,8 +813,44 @@ __global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ in
             xr = x;
             yr = y;
         }
-        const double rho_o = init_density(ini, P, 0, xr, yr);
-        const double rho_w = init_density(ini, P, 1, xr, yr);
+        double rho_o = init_density(ini, P, 0, xr, yr);
+        double rho_w = init_density(ini, P, 1, xr, yr);
+        if constexpr (!S::kRef) {
+            // Interpolated walls: x reads this slot as the half-way value of
+            // direction j = opp(i); when the wall is at q >= 1/2 the first
+            // pull blends it with slot (x, j), which holds w rho0(x + c_j) for
+            // the node x + c_j that pulls it.  Store the value that makes the
+            // blend w_i rho0(x), the rest state.  (For q < 1/2 the blend
+            // partner already holds w_i rho0(x).)
+            if (P.wq && xr == x && yr == y && i > 0) {
+                const int j = kOpp[i];
+                const float q = ibb_q(P, x, y, cols[P.col_off + x], j);
+                const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j];
+                if (q >= 0.5f && fluid(xo, yo)) {
+                    const double two_q = 2.0 * (double)q;
+                    rho_o = two_q * rho_o - (two_q - 1.0) * init_density(ini, P, 0, xo, yo);
+                    rho_w = two_q * rho_w - (two_q - 1.0) * init_density(ini, P, 1, xo, yo);
+                }
+            }
+            // The first pull takes from the rest population what those
+            // blends add to their half-way slots, (2q - 1) w_j (rho0(x + c_j)
+            // - rho0(x)) per link; store it in advance so that the pulled rest
+            // population is w_0 rho0(x).
+            if (P.wq && i == 0) {
+                const double ro = rho_o, rw = rho_w;
+                for (int j = 1; j < 9; ++j) {
+                    if (fluid(wrapi(x - kCx[j], P.nx), y - kCy[j]))
+                        continue;
+                    const float q = ibb_q(P, x, y, cols[P.col_off + x], j);
+                    const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j];
+                    if (q >= 0.5f && fluid(xo, yo)) {
+                        const double c = (2.0 * (double)q - 1.0) * (kW36[j] / kW36[0]);
+                        rho_o += c * (init_density(ini, P, 0, xo, yo) - ro);
+                        rho_w += c * (init_density(ini, P, 1, xo, yo) - rw);
+                    }
+                }
+            }
+        }
         if constexpr (S::kRef)
             *reinterpret_cast<uint32_t*>(node + i * plane) =
                 S::rne((float)(rho_o - (double)R[0])) |
@@ -726,36 +860,37 @@ __global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ in
     }
 }
 
-// r3: kernels with the third-order regularization branch (instances with
-// reg3 take it); only the colliding modes have such a variant.
+// ext: the extended kernels, with the branches of the optional features
+// (third-order regularization, interpolated walls) that instances with
+// those flags take.  Monitors and exports need the extended pull too.
 template <int BX, typename T>
-hipError_t launch_step_bx(int mode, bool r3, const void* fin, void* fout, const InstDev* insts,
+hipError_t launch_step_bx(int mode, bool ext, const void* fin, void* fout, const InstDev* insts,
                           const Item* items, int item_base, int n_items, const Col* cols,
                           double* partial, double* stage, uint32_t seed,
                           const uint32_t* seed_dev, hipStream_t stream)
 {
     const dim3 grid(n_items), block(BX);
-#define LBM_LAUNCH(M, R)                                                                   \
-    step_kernel<BX, M, T, R><<<grid, block, 0, stream>>>(fin, fout, insts, items, item_base, \
-                                                         cols, partial, stage, seed, seed_dev)
+#define LBM_LAUNCH(M)                                                                      \
+    do {                                                                                   \
+        if (ext)                                                                           \
+            step_kernel<BX, M, T, true><<<grid, block, 0, stream>>>(                       \
+                fin, fout, insts, items, item_base, cols, partial, stage, seed, seed_dev); \
+        else                                                                               \
+            step_kernel<BX, M, T, false><<<grid, block, 0, stream>>>(                      \
+                fin, fout, insts, items, item_base, cols, partial, stage, seed, seed_dev); \
+    } while (0)
     switch (mode) {
     case kStep:
-        if (r3)
-            LBM_LAUNCH(kStep, true);
-        else
-            LBM_LAUNCH(kStep, false);
+        LBM_LAUNCH(kStep);
         break;
     case kStepMon:
-        if (r3)
-            LBM_LAUNCH(kStepMon, true);
-        else
-            LBM_LAUNCH(kStepMon, false);
+        LBM_LAUNCH(kStepMon);
         break;
     case kMonOnly:
-        LBM_LAUNCH(kMonOnly, false);
+        LBM_LAUNCH(kMonOnly);
         break;
     case kExport:
-        LBM_LAUNCH(kExport, false);
+        LBM_LAUNCH(kExport);
         break;
     default:
         return hipErrorInvalidValue;
@@ -765,20 +900,20 @@ hipError_t launch_step_bx(int mode, bool r3, const void* fin, void* fout, const 
 }
 
 template <typename T>
-hipError_t launch_step_t(int bx, int mode, bool r3, const void* fin, void* fout, const InstDev* insts,
+hipError_t launch_step_t(int bx, int mode, bool ext, const void* fin, void* fout, const InstDev* insts,
                          const Item* items, int item_base, int n_items, const Col* cols,
                          double* partial, double* stage, uint32_t seed, const uint32_t* seed_dev,
                          hipStream_t stream)
 {
     switch (bx) {
     case 64:
-        return launch_step_bx<64, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<64, T>(mode, ext, fin, fout, insts, items, item_base, n_items, cols,
                                      partial, stage, seed, seed_dev, stream);
     case 128:
-        return launch_step_bx<128, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<128, T>(mode, ext, fin, fout, insts, items, item_base, n_items, cols,
                                       partial, stage, seed, seed_dev, stream);
     case 256:
-        return launch_step_bx<256, T>(mode, r3, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_bx<256, T>(mode, ext, fin, fout, insts, items, item_base, n_items, cols,
                                       partial, stage, seed, seed_dev, stream);
     default:
         return hipErrorInvalidValue;
@@ -787,7 +922,7 @@ hipError_t launch_step_t(int bx, int mode, bool r3, const void* fin, void* fout,
 
 }  // namespace
 
-hipError_t launch_step(int storage, int bx, int mode, bool r3, const void* fin, void* fout,
+hipError_t launch_step(int storage, int bx, int mode, bool ext, const void* fin, void* fout,
                        const InstDev* insts, const Item* items, int item_base, int n_items,
                        const Col* cols, double* partial, double* stage, uint32_t seed,
                        const uint32_t* seed_dev, hipStream_t stream)
@@ -796,13 +931,13 @@ hipError_t launch_step(int storage, int bx, int mode, bool r3, const void* fin, 
         return hipSuccess;
     switch (storage) {
     case 0:
-        return launch_step_t<float>(bx, mode, r3, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_t<float>(bx, mode, ext, fin, fout, insts, items, item_base, n_items, cols,
                                     partial, stage, seed, seed_dev, stream);
     case 1:
-        return launch_step_t<F16Tag>(bx, mode, r3, fin, fout, insts, items, item_base, n_items, cols,
+        return launch_step_t<F16Tag>(bx, mode, ext, fin, fout, insts, items, item_base, n_items, cols,
                                      partial, stage, seed, seed_dev, stream);
     case 2:
-        return launch_step_t<BF16Tag>(bx, mode, r3, fin, fout, insts, items, item_base, n_items,
+        return launch_step_t<BF16Tag>(bx, mode, ext, fin, fout, insts, items, item_base, n_items,
                                       cols, partial, stage, seed, seed_dev, stream);
     default:
         return hipErrorInvalidValue;

@@ -60,7 +60,7 @@ bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
         return true;
     }
     if (g.kind == LBM_GEOM_CHANNEL) {
-        const double yc = 0.5 * (g.ny - 1);
+        const double yc = 0.5 * (g.ny - 1) + g.y_offset;
         for (int x = 0; x < g.nx; ++x) {
             const double h = g.h0 + g.a * std::cos(2.0 * M_PI * (double)x / g.lambda);
             int lo = g.ny, hi = -1;
@@ -99,8 +99,66 @@ bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
     return false;
 }
 
+// Wall table of a channel with interpolated walls ([nx][kWallSlots][8]
+// floats, 1 where a slot has no wall link): for every fluid node (x, y) and
+// pulled direction j whose source node x - c_j is solid, the fraction q in
+// (0, 1] of the link from (x, y) along -c_j at which it leaves the fluid region
+// |y - y_c| < h(x), in FP64: in closed form for flat walls, otherwise by 60
+// halvings of the link, keeping the first point found outside.  Fails if a
+// node outside the wall slots has a wall link (walls steeper than one row per
+// column).
+bool wall_table(const lbm_geom& g, const std::vector<Col>& cols, std::vector<float>& wq,
+                std::string& err)
+{
+    static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double yc = 0.5 * (g.ny - 1) + g.y_offset;
+    auto inside = [&](double X, double Y) {  // the expression voxelise classifies by
+        return std::fabs(Y - yc) < g.h0 + g.a * std::cos(2.0 * M_PI * X / g.lambda);
+    };
+    wq.assign((size_t)g.nx * kWallSlots * 8, 1.0f);
+    for (int x = 0; x < g.nx; ++x) {
+        const Col c = cols[x];
+        for (int y = c.lo; y <= c.hi; ++y)
+            for (int j = 1; j < 9; ++j) {
+                const Col& cs = cols[(x - cx[j] + g.nx) % g.nx];
+                const int ys = y - cy[j];
+                if (ys >= cs.lo && ys <= cs.hi)
+                    continue;
+                const int slot = wall_slot(y, c.lo, c.hi);
+                if (slot < 0) {
+                    err = "interpolated walls: node (" + std::to_string(x) + ", " +
+                          std::to_string(y) +
+                          ") two rows inside the wall has a wall link (walls steeper "
+                          "than one row per column)";
+                    return false;
+                }
+                double q;
+                if (g.a == 0.0) {
+                    q = (g.h0 - std::fabs((double)y - yc)) / std::fabs((double)cy[j]);
+                } else {
+                    double lo = 0.0, hi = 1.0;
+                    for (int it = 0; it < 60; ++it) {
+                        const double t = 0.5 * (lo + hi);
+                        if (inside((double)x - t * cx[j], (double)y - t * cy[j]))
+                            lo = t;
+                        else
+                            hi = t;
+                    }
+                    q = hi;
+                }
+                wq[((size_t)x * kWallSlots + slot) * 8 + (j - 1)] = (float)q;
+            }
+    }
+    return true;
+}
+
 lbm_status check_geom(const lbm_geom& g)
 {
+    if (g.wall_interp != 0 && g.wall_interp != 1)
+        return fail(LBM_ERR_INVALID, "wall_interp must be 0 or 1");
+    if (g.wall_interp && g.kind != LBM_GEOM_CHANNEL)
+        return fail(LBM_ERR_UNSUPPORTED, "interpolated walls need the analytic channel geometry");
     if (g.nx < 1 || g.ny < 1 || g.nx > 32768 || g.ny > 32768)
         return fail(LBM_ERR_INVALID, "geometry size %d x %d out of range", g.nx, g.ny);
     // The kernels address an instance with 32-bit byte offsets.
@@ -115,6 +173,8 @@ lbm_status check_geom(const lbm_geom& g)
     if (g.kind == LBM_GEOM_CHANNEL) {
         if (!(g.lambda > 0.0) || !(g.h0 > 0.0) || !(g.a >= 0.0) || !std::isfinite(g.h0 + g.a))
             return fail(LBM_ERR_INVALID, "channel needs lambda > 0, h0 > 0, a >= 0");
+        if (!(std::fabs(g.y_offset) <= 1.0))
+            return fail(LBM_ERR_INVALID, "channel y_offset must lie in [-1, 1]");
         if (g.nx < 3)
             return fail(LBM_ERR_INVALID, "channel needs nx >= 3");
         return LBM_OK;
@@ -171,13 +231,15 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
     const int storage = storage_and_opts & 0xff;
     const bool with_snap = (storage_and_opts & LBM_OPT_SNAPSHOT) != 0;
     Layout L{};
-    int64_t elems = 0, ncols = 0;
+    int64_t elems = 0, ncols = 0, nwq = 0;
     L.n_items_max = 0;
     L.max_nodes = 0;
     for (int k = 0; k < n_inst; ++k) {
         const lbm_geom& g = geoms[k];
         elems += inst_elems(g.nx, g.ny, storage);
         ncols += g.nx;
+        if (g.wall_interp)
+            nwq += (int64_t)g.nx * kWallSlots * 8;
         L.n_items_max += max_items(g);
         L.max_nodes = std::max<int64_t>(L.max_nodes, (int64_t)g.nx * g.ny);
     }
@@ -208,6 +270,8 @@ Layout layout_of(const lbm_geom* geoms, int n_inst, int storage_and_opts)
     o = align_up(o + sizeof(double) * kExportFields * L.max_nodes, kAlign);
     L.off_seed = o;
     o = align_up(o + sizeof(uint32_t), kAlign);
+    L.off_wq = o;
+    o = align_up(o + sizeof(float) * nwq, kAlign);
     L.total = o;
     return L;
 }
@@ -235,12 +299,12 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
     d.Gd = f.G;
 }
 
-// Whether any instance uses the third-order regularization (then the step
-// launches the kernels with that branch).
-bool any_reg3(const lbm_ctx* c)
+// Whether any instance uses an optional feature (third-order regularization,
+// interpolated walls): then the step launches the extended kernels.
+bool any_ext(const lbm_ctx* c)
 {
     for (const InstDev& d : c->idv)
-        if (d.reg3)
+        if (d.reg3 || d.wq)
             return true;
     return false;
 }
@@ -358,7 +422,7 @@ lbm_status sync_all(lbm_ctx* c)
 lbm_status run_range(lbm_ctx* c, int bx, int mode, int item_base, int n_items,
                      uint32_t seed = 0, const uint32_t* seed_dev = nullptr)
 {
-    hipError_t e = launch_step(c->storage, bx, mode, any_reg3(c), c->buf[c->cur],
+    hipError_t e = launch_step(c->storage, bx, mode, any_ext(c), c->buf[c->cur],
                                c->buf[c->cur ^ 1], c->inst_d, c->items_d, item_base, n_items,
                                c->cols_d,
                                c->partial_d, c->stage_d, seed, seed_dev, c->stream);
@@ -424,6 +488,9 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     if ((uintptr_t)device_workspace % kAlign)
         return fail(LBM_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
     for (int k = 0; k < n_inst; ++k) {
+        if (geoms[k].wall_interp && (storage & 0xff) != LBM_STORE_F32)
+            return fail(LBM_ERR_UNSUPPORTED,
+                        "instance %d: interpolated walls need FP32 storage", k);
         lbm_status st = check_geom(geoms[k]);
         if (st != LBM_OK)
             return st;
@@ -476,6 +543,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     c->ih.resize(n_inst);
     c->idv.resize(n_inst);
     std::vector<Col> all_cols;
+    std::vector<float> all_wq;
     int64_t f_off = 0;
     int max_nx = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -502,6 +570,16 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         d.ny = g.ny;
         d.pitch = h.pitch;
         d.periodic_y = g.kind == LBM_GEOM_BOX ? 1 : 0;
+        d.wq = nullptr;
+        if (g.wall_interp) {
+            std::vector<float> wq;
+            if (!wall_table(g, h.cols, wq, err)) {
+                delete c;
+                return fail(LBM_ERR_UNSUPPORTED, "instance %d: %s", k, err.c_str());
+            }
+            d.wq = (const float*)(c->ws + L.off_wq) + all_wq.size();
+            all_wq.insert(all_wq.end(), wq.begin(), wq.end());
+        }
         d.col_off = (int32_t)all_cols.size();
         fill_inst_params(d, fluids[k]);
         all_cols.insert(all_cols.end(), h.cols.begin(), h.cols.end());
@@ -534,6 +612,9 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
                             hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(c->cols_d, all_cols.data(), sizeof(Col) * all_cols.size(),
                             hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+        (!all_wq.empty() &&
+         (e = hipMemcpyAsync(c->ws + L.off_wq, all_wq.data(), sizeof(float) * all_wq.size(),
+                             hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
         (e = hipMemsetAsync(c->ws + L.off_buf[0], 0, 2 * L.buf_bytes, c->stream)) !=
             hipSuccess)
         return bail(fail(LBM_ERR_DEVICE, "lbm_init upload failed: %s", hipGetErrorString(e)));
@@ -713,9 +794,9 @@ lbm_status lbm_set_fluid(lbm_ctx* c, int32_t inst, const lbm_fluid* fluid)
     lbm_status st = check_fluid(*fluid);
     if (st != LBM_OK)
         return st;
-    const bool r3_before = any_reg3(c);
+    const bool ext_before = any_ext(c);
     fill_inst_params(c->idv[inst], *fluid);
-    if (any_reg3(c) != r3_before)
+    if (any_ext(c) != ext_before)
         c->graph_dirty = true;  // the captured launches name the other kernels
     HIP_TRY(hipMemcpyAsync(c->inst_d + inst, &c->idv[inst], sizeof(InstDev),
                            hipMemcpyHostToDevice, c->stream));

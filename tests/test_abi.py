@@ -181,3 +181,27 @@ def test_lbm3d_critical_pressure_validates_on_the_host():
         st = lib.lbm3d_critical_pressure(arr, 1, ctypes.byref(opts), ctypes.c_void_p(1 << 20),
                                          1 << 30, None, res)
         assert st == 1 and what in lib.lbm_last_error().decode()
+
+
+def test_interpolated_walls_validate_on_the_host():
+    fl = [binding.fluid_struct((1.0, 1.0), -2.7)]
+    ini = [binding.init_struct("uniform")]
+    flat = dict(lam=64.0, h0=8.0, a=0.0)
+    plain = binding.lbm_required_bytes([binding.geom_struct("channel", 64, 18, **flat)])
+    interp = binding.lbm_required_bytes(
+        [binding.geom_struct("channel", 64, 18, wall_interp=1, **flat)])
+    assert interp - plain >= 64 * 32 * 4      # the wall table: 32 floats per column
+    cases = [
+        (binding.geom_struct("box", 32, 32, wall_interp=1), "f32", 6, "analytic channel"),
+        (binding.geom_struct("channel", 64, 18, wall_interp=1, **flat), "f16", 6, "FP32"),
+        (binding.geom_struct("channel", 64, 18, wall_interp=2, **flat), "f32", 1, "0 or 1"),
+        (binding.geom_struct("channel", 64, 18, y_offset=1.5, **flat), "f32", 1, "y_offset"),
+        # slope a 2 pi / lambda = 1.57: fluid runs of neighbouring columns
+        # differ by two rows
+        (binding.geom_struct("channel", 32, 20, wall_interp=1, lam=16.0, h0=6.0, a=4.0),
+         "f32", 6, "steeper"),
+    ]
+    for g, storage, status, text in cases:
+        with pytest.raises(_lib.LbmError) as e:
+            binding.lbm_init([g], fl, ini, storage, 1 << 20, 1 << 30, 0)
+        assert e.value.status == status and text in str(e.value), (text, str(e.value))
