@@ -173,8 +173,8 @@ def cpu_baseline(seconds):
 
 
 # Sources of the D2Q9 step kernel; the counter record names their hash.
-KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_store.h")
-KERNEL3_SOURCES = ("lbm3d_kernels.hip", "lbm_store.h")
+KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_store.h", "lbm_internal.h")
+KERNEL3_SOURCES = ("lbm3d_kernels.hip", "lbm_store.h", "lbm3d_internal.h")
 
 
 def measured_traffic(storage, record="step_kernel_batch256_traffic.txt",

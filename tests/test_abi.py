@@ -129,7 +129,8 @@ def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     (fake_root / "paper_1601_00918_amd" / "csrc").mkdir(parents=True)
     (fake_root / "profiles" / "step_kernel_batch256_traffic.txt").write_text(json.dumps(rec))
     (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_kernels.hip").write_text("// other\n")
-    (fake_root / "paper_1601_00918_amd" / "csrc" / "lbm_store.h").write_text("// other\n")
+    for f in ("lbm_store.h", "lbm_internal.h"):
+        (fake_root / "paper_1601_00918_amd" / "csrc" / f).write_text("// other\n")
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     assert bench.measured_traffic("f32") is None
 
