@@ -137,3 +137,46 @@ def meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8, walls=None):
     mean_x = float(np.mean(xs))
     centre_on_oil = (xc < mean_x) if oil_left else (xc > mean_x)
     return contact_angle(R, y0, centre_on_oil), R, (np.array(xs), np.array(ys))
+
+
+def tube_meniscus_contact_angle(frac, mask, x_guess, oil_left, window=8, axis=None):
+    """Sec. 3.3 contact-angle detection carried to a slug in a straight tube
+    (the axisymmetric counterpart of meniscus_contact_angle).
+
+    frac: oil fraction [nz][ny][nx]; mask: fluid mask [nz][ny][nx] of a tube
+    along x with the same cross-section at every x; axis = (y_c, z_c), default
+    the box centre.  Eq. 12 is fitted along x on every fluid line of the
+    cross-section whose four in-plane neighbours are fluid (the ring next to
+    the wall is left out, as the rows next to the walls are in the planar
+    case), a sphere centred on the axis is fitted to the interface points in
+    the meridian plane, (x - x_c)^2 + r^2 = R^2, and Eq. 14 is applied with
+    the tube radius r_w = sqrt(A / pi), A the number of fluid nodes in the
+    cross-section (the area the half-way walls enclose).  Returns (theta
+    through water in degrees, R, (x points, r points))."""
+    frac = np.asarray(frac, dtype=float)
+    sec = np.asarray(mask, dtype=bool)[:, :, 0]
+    nz, ny, nx = frac.shape
+    if axis is None:
+        axis = (0.5 * (ny - 1), 0.5 * (nz - 1))
+    r_w = math.sqrt(float(sec.sum()) / math.pi)
+    inner = sec.copy()
+    inner[1:, :] &= sec[:-1, :]
+    inner[:-1, :] &= sec[1:, :]
+    inner[:, 1:] &= sec[:, :-1]
+    inner[:, :-1] &= sec[:, 1:]
+    inner[0, :] = inner[-1, :] = False
+    inner[:, 0] = inner[:, -1] = False
+    x = np.arange(int(round(x_guess)) - window, int(round(x_guess)) + window + 1)
+    xs, rs = [], []
+    for z, y in zip(*np.nonzero(inner)):
+        prof = frac[z, y, np.mod(x, nx)]
+        c = fit_interface(x, prof, x_guess)
+        xs.append(c[2])
+        rs.append(math.hypot(y - axis[0], z - axis[1]))
+    xs, rs = np.array(xs), np.array(rs)
+    A = np.stack([2.0 * xs, np.ones_like(xs)], axis=1)
+    (xc, c), *_ = np.linalg.lstsq(A, xs * xs + rs * rs, rcond=None)
+    R = math.sqrt(c + xc * xc)
+    mean_x = float(np.mean(xs))
+    centre_on_oil = (xc < mean_x) if oil_left else (xc > mean_x)
+    return contact_angle(R, r_w, centre_on_oil), R, (xs, rs)

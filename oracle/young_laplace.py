@@ -24,6 +24,11 @@ same quantity from the Young-Laplace law (Eq. 11) and the contact angle
   (wall-bounded volume between the contact lines plus the two signed caps).
   The critical Delta P is the maximum of Delta P(x_r) over one period, and
   Bo_crit = Delta P_crit D / sigma (Eq. 15, D the neck half-width / radius).
+* Contact-angle variation (Sec. 3.4.2, Table 3's fifth column): the front and
+  rear menisci may meet the wall at different angles theta_f, theta_r; with
+  the angle known only to lie in a range [theta_lo, theta_hi] (Table 1's
+  spread over wall offsets), the highest critical pressure over the pairs of
+  angles in the range is the one compared with.
 """
 import math
 
@@ -87,46 +92,68 @@ def meniscus(channel, x, theta, front):
     return p, math.copysign(vol, c)
 
 
-def slug_volume(channel, xr, xf, theta):
+def slug_volume(channel, xr, xf, theta, theta_rear=None):
+    """Wall-bounded volume between the contact lines plus the two signed caps
+    (front meniscus at theta, rear at theta_rear, default theta)."""
+    tr = theta if theta_rear is None else theta_rear
     _, vf = meniscus(channel, xf, theta, True)
-    _, vr = meniscus(channel, xr, theta, False)
+    _, vr = meniscus(channel, xr, tr, False)
     return channel.body_volume(xr, xf) + vf + vr
 
 
-def front_position(channel, xr, theta, volume):
+def front_position(channel, xr, theta, volume, theta_rear=None):
     """x_f > x_r with slug_volume = volume (volume grows monotonically with x_f
     over the bracket searched)."""
     lo = xr + 1e-9
     hi = xr + 1e-3
-    while slug_volume(channel, xr, hi, theta) < volume:
+    while slug_volume(channel, xr, hi, theta, theta_rear) < volume:
         hi += 0.25 * channel.lam
         if hi - xr > 20 * channel.lam:
             raise ValueError("slug volume not reachable")
-    return brentq(lambda xf: slug_volume(channel, xr, xf, theta) - volume, lo, hi,
+    return brentq(lambda xf: slug_volume(channel, xr, xf, theta, theta_rear) - volume, lo, hi,
                   xtol=1e-12, rtol=1e-14)
 
 
-def pressure_drop(channel, xr, theta, volume):
-    """Delta P / sigma = (P_f - P_r) / sigma for the slug with rear at x_r."""
-    xf = front_position(channel, xr, theta, volume)
+def pressure_drop(channel, xr, theta, volume, theta_rear=None):
+    """Delta P / sigma = (P_f - P_r) / sigma for the slug with rear at x_r
+    (front angle theta, rear angle theta_rear, default theta; radians)."""
+    tr = theta if theta_rear is None else theta_rear
+    xf = front_position(channel, xr, theta, volume, theta_rear)
     pf, _ = meniscus(channel, xf, theta, True)
-    pr, _ = meniscus(channel, xr, theta, False)
+    pr, _ = meniscus(channel, xr, tr, False)
     return pf - pr
 
 
-def critical_pressure(channel, theta_deg, volume, n_scan=241):
+def critical_pressure(channel, theta_deg, volume, n_scan=241, theta_rear_deg=None):
     """max over rear positions of Delta P / sigma (the static slug gives way
-    once the driving pressure exceeds it).  Returns (dP/sigma, x_r at max)."""
+    once the driving pressure exceeds it), front meniscus at theta_deg and rear
+    at theta_rear_deg (default the same).  Returns (dP/sigma, x_r at max)."""
     th = math.radians(theta_deg)
+    tr = None if theta_rear_deg is None else math.radians(theta_rear_deg)
     xs = np.linspace(0.0, channel.lam, n_scan, endpoint=False)
-    vals = np.array([pressure_drop(channel, x, th, volume) for x in xs])
+    vals = np.array([pressure_drop(channel, x, th, volume, tr) for x in xs])
     k = int(np.argmax(vals))
     step = channel.lam / n_scan
-    res = minimize_scalar(lambda x: -pressure_drop(channel, x, th, volume),
+    res = minimize_scalar(lambda x: -pressure_drop(channel, x, th, volume, tr),
                           bounds=(xs[k] - step, xs[k] + step), method="bounded",
                           options={"xatol": 1e-9})
     best = max(vals[k], -res.fun)
     return best, (res.x if -res.fun >= vals[k] else xs[k])
+
+
+def critical_pressure_range(channel, theta_lo_deg, theta_hi_deg, volume, n_scan=241):
+    """Highest critical Delta P / sigma over front and rear angles in
+    [theta_lo, theta_hi].  Each meniscus pressure is monotonic in its own
+    angle (cos(theta -+ phi) over (0, pi)), so the highest value is taken at
+    the ends of the range: all four pairs are evaluated.  Returns
+    (dP/sigma, (theta_front, theta_rear) in degrees)."""
+    best, arg = -np.inf, None
+    for tf in (theta_lo_deg, theta_hi_deg):
+        for tr in (theta_lo_deg, theta_hi_deg):
+            dp, _ = critical_pressure(channel, tf, volume, n_scan, theta_rear_deg=tr)
+            if dp > best:
+                best, arg = dp, (tf, tr)
+    return best, arg
 
 
 def paper_tube(D=1.0):
@@ -141,6 +168,15 @@ def bond_critical_tube(theta_deg, volume_over_D3):
     for a slug of volume V0 / D^3 (Eq. 15-16)."""
     dp, _ = critical_pressure(paper_tube(1.0), theta_deg, volume_over_D3)
     return dp * 1.0
+
+
+def bond_critical_tube_range(theta_lo_deg, theta_hi_deg, volume_over_D3):
+    """Analytic critical Bond number of the paper's tube when the contact
+    angle is known only to lie in [theta_lo, theta_hi] (the highest over the
+    front and rear angles in the range)."""
+    dp, _ = critical_pressure_range(paper_tube(1.0), theta_lo_deg, theta_hi_deg,
+                                    volume_over_D3)
+    return dp
 
 
 def bond_critical_channel(lam, h0, a, theta_deg, area):

@@ -320,3 +320,73 @@ def test_interpolated_walls_keep_each_species_mass():
     m0 = L.moments()["mon"][:2].copy()
     L.step(400)
     np.testing.assert_allclose(L.moments()["mon"][:2], m0, rtol=1e-12)
+
+
+# ---- contact-angle variation (hysteresis) in the Young-Laplace estimate ------
+def test_young_laplace_equal_front_and_rear_angles_is_the_plain_estimate():
+    ch = yl.paper_tube(1.0)
+    a = yl.critical_pressure(ch, 41.5, 57.4)[0]
+    b = yl.critical_pressure(ch, 41.5, 57.4, theta_rear_deg=41.5)[0]
+    assert a == b
+    assert yl.bond_critical_tube_range(41.5, 41.5, 57.4) == a
+
+
+@pytest.mark.parametrize("axi", [False, True])
+def test_young_laplace_straight_channel_with_angle_hysteresis_closed_form(axi):
+    """a = 0: both menisci sit on parallel walls, so the resistance is the
+    pure hysteresis term k (cos theta_f - cos theta_r) / h (k = 1 planar,
+    2 axisymmetric), independent of where the slug sits."""
+    h = 7.0
+    ch = yl.Channel(h, 0.0, 40.0, axisymmetric=axi)
+    k = 2.0 if axi else 1.0
+    vol = (600.0 if not axi else 4000.0)
+    for tf, tr in ((40.0, 46.0), (138.0, 145.0), (60.0, 120.0)):
+        dp, _ = yl.critical_pressure(ch, tf, vol, theta_rear_deg=tr)
+        want = k * (math.cos(math.radians(tf)) - math.cos(math.radians(tr))) / h
+        assert dp == pytest.approx(want, rel=1e-10, abs=1e-13)
+    dp, arg = yl.critical_pressure_range(ch, 40.0, 46.0, vol)
+    assert arg == (40.0, 46.0)
+    assert dp == pytest.approx(k * (math.cos(math.radians(40.0)) -
+                                    math.cos(math.radians(46.0))) / h, rel=1e-10)
+
+
+def test_young_laplace_angle_range_maximum_sits_at_the_ends():
+    """The highest critical pressure over a grid of front and rear angles in
+    the range is the one at the range ends (each meniscus pressure is
+    monotonic in its angle), and it grows with the width of the range."""
+    ch = yl.paper_tube(1.0)
+    lo, hi, vol = 39.6, 44.1, 57.4
+    best, arg = yl.critical_pressure_range(ch, lo, hi, vol, n_scan=121)
+    assert arg == (lo, hi)          # front at the smaller, rear at the larger angle
+    grid = np.linspace(lo, hi, 4)
+    inner = max(yl.critical_pressure(ch, tf, vol, n_scan=121, theta_rear_deg=tr)[0]
+                for tf in grid for tr in grid)
+    assert inner <= best + 1e-9
+    wider, _ = yl.critical_pressure_range(ch, lo - 1.0, hi + 1.0, vol, n_scan=121)
+    assert wider > best > yl.critical_pressure(ch, 41.5, vol, n_scan=121)[0]
+
+
+@pytest.mark.parametrize("theta", [40.0, 90.5, 140.0])
+def test_tube_contact_angle_detection_recovers_a_known_cap(theta):
+    """The detection carried to a straight voxelised tube (radius 9.5): a
+    synthetic slug whose front meniscus is an exact spherical cap meeting the
+    tube's area-equivalent wall radius at theta, tanh width 1.5, is recovered
+    to 0.5 deg."""
+    from oracle import analysis as an
+    nx, n = 120, 23
+    yc = zc = 0.5 * (n - 1)
+    Z, Y, X = np.mgrid[0:n, 0:n, 0:nx].astype(float)
+    mask = ((Y - yc) ** 2 + (Z - zc) ** 2 < 9.5 ** 2).astype(np.uint8)
+    r_w = math.sqrt(mask[:, :, 0].sum() / math.pi)
+    a = math.radians(theta)
+    xm = 70.0
+    r = np.hypot(Y - yc, Z - zc)
+    if abs(math.cos(a)) < 1e-9:
+        xs = np.full_like(r, xm)
+    else:
+        R = r_w / abs(math.cos(a))
+        sgn = 1.0 if theta < 90 else -1.0
+        xs = xm - sgn * R + sgn * np.sqrt(np.maximum(R * R - r * r, 0.0))
+    frac = 0.5 * (1.0 - np.tanh((X - xs) / 1.5)) * mask
+    got, _, _ = an.tube_meniscus_contact_angle(frac, mask, xm - 3.0, oil_left=True, window=12)
+    assert got == pytest.approx(theta, abs=0.5)
