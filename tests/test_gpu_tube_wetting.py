@@ -1,0 +1,132 @@
+"""Wettability in the D3Q19 tubes (Secs. 3.3 and 3.4.2): the contact angle of
+the wall potentials in straight tubes, its spread over the tube axis's offset
+from the lattice (the 3-D counterpart of Table 1), and the critical Bond
+number of water-wet and oil-wet slugs in the paper's tube at four initial
+positions against the axisymmetric Young-Laplace estimate without and with
+that spread (Table 3 analogue)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import analysis as an
+
+pytestmark = pytest.mark.gpu
+
+NOMINAL = (30.0, 90.0, 150.0)
+# tube axis offsets (dy, dz) from the lattice, in lattice spacings
+OFFSETS = ((0.0, 0.0), (0.5, 0.0), (0.5, 0.5), (0.25, 0.25), (0.25, 0.0))
+
+
+def _straight_tube(r, theta, dy, dz, nx=112, length=56):
+    """Straight tube of radius r along x whose axis sits (dy, dz) off the
+    node-centred position, oil slug of `length` nodes at rest."""
+    n = int(2 * r + 4)
+    cfg = synth.config_tube(lam=float(nx), r0=r, a=0.0, nx=nx, ny=n, nz=n, theta=theta,
+                            slug_len=length, slug_x0=(nx - length) // 2)
+    yc, zc = 0.5 * (n - 1) + dy, 0.5 * (n - 1) + dz
+    y = np.arange(n, dtype=float)[None, :, None]
+    z = np.arange(n, dtype=float)[:, None, None]
+    sec = ((y - yc) ** 2 + (z - zc) ** 2 < r * r)
+    mask = np.broadcast_to(sec, (n, n, nx)).astype(np.uint8).copy()
+    return dict(cfg, kind="mask", mask=mask), (yc, zc)
+
+
+def _tube_angle(sim, cfg, axis):
+    rho = sim.moments()["rho"]
+    frac = rho[0] / np.maximum(rho[0] + rho[1], 1e-30)
+    x0, L = cfg["init"]["x0"], cfg["init"]["length"]
+    f, _, _ = an.tube_meniscus_contact_angle(frac, cfg["mask"], x0 + L, True, axis=axis)
+    r, _, _ = an.tube_meniscus_contact_angle(frac, cfg["mask"], x0, False, axis=axis)
+    return 0.5 * (f + r), f, r
+
+
+def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
+    """Slugs at rest in straight tubes of radius 8 (the paper's neck radius)
+    after 30,000 steps, tau = 1: the angle of each wall-potential pair for
+    five axis offsets.  The map must stay symmetric about 90 deg and the
+    spread over the offsets (the lattice-orientation variation the paper's
+    fifth column accounts for) is reported."""
+    from paper_1601_00918_amd.binding3d import Simulation3D
+    res = {}
+    for th in NOMINAL:
+        for off in OFFSETS:
+            cfg, axis = _straight_tube(8.0, th, *off)
+            sim = Simulation3D(cfg)
+            sim.step(30000)
+            res[th, off] = _tube_angle(sim, cfg, axis)
+            print("nominal %5.1f offset %-12s theta %.2f (front %.2f rear %.2f)"
+                  % ((th, str(off)) + res[th, off]), flush=True)
+    for th in NOMINAL:
+        vals = [res[th, o][0] for o in OFFSETS]
+        print("nominal %5.1f: %.2f - %.2f" % (th, min(vals), max(vals)))
+    for o in OFFSETS:
+        assert abs(res[90.0, o][0] - 90.0) <= 1.0
+        assert abs(res[30.0, o][0] + res[150.0, o][0] - 180.0) <= 1.0
+    for th in NOMINAL:
+        vals = [res[th, o][0] for o in OFFSETS]
+        assert max(vals) - min(vals) <= 8.0
+
+
+# 3-D contact angles of the nominal 30 / 150 deg potentials in straight tubes
+# of radius 8 over the five axis offsets (measured by the test above).
+THETA3 = {30.0: (40.12, 40.55), 150.0: (139.45, 139.88)}
+
+
+@pytest.mark.parametrize("wet,nominal,target,spread", [("water-wet", 30.0, 56.0, 0.08),
+                                                       ("oil-wet", 150.0, 69.0, 0.03)])
+def test_paper_tube_wettability_four_positions(gpu_available, wet, nominal, target, spread):
+    """Table 3 analogue: the paper's tube at D = 8 (three periods over L = 18 D,
+    radius D at the neck, 2.5 D at the widest), tau = 1, a water-wet (about
+    40 deg) or oil-wet (about 140 deg) wall, slugs of about the volume Table 2
+    targets (56 and 69 D^3) at four positions a quarter wavelength apart;
+    40,000 unforced steps, the 90 % volume rule, then the ramp of Delta Bo =
+    0.02 every 40,000 steps.  The critical Bo is compared with the axisymmetric
+    Young-Laplace value for the measured angle and volume (Delta theta = 0)
+    and with the highest value over the angle spread of the axis offsets
+    (Delta theta != 0).  The ratio to the analytic value must lie within 20 %
+    (the neutral case of the same tube sits at 0.85) and not depend on the
+    position beyond 0.03 (oil-wet) or 0.08 (water-wet: there the first
+    position mobilises one level in three lower, 0.06 in Bo, as the paper
+    notes for its water-wet slugs)."""
+    from oracle import young_laplace as yl
+    from paper_1601_00918_amd import binding, binding3d as b3
+    D, sig, rho_bar = 8, 0.195, 1.03
+    base = dict(lam=48, r0=14.0, a=6.0, nx=144, theta=nominal, tau=(1.0, 1.0))
+    col = synth.mask3_of(synth.config_tube(**base)).sum(axis=(0, 1))
+    cfgs = []
+    for j in range(4):
+        x0 = 4 + 12 * j
+        n = int(np.searchsorted(np.cumsum(np.roll(col, -x0)), target * D ** 3)) + 1
+        cfgs.append(synth.config_tube(slug_x0=x0, slug_len=n, **base))
+    L = cfgs[0]["nx"]
+    to_g = sig / (rho_bar * L * D)
+    vols = []
+    for c in cfgs:
+        sim = b3.Simulation3D(c)
+        sim.step(40000)
+        rho = sim.moments()["rho"]
+        frac = rho[0] / np.maximum(rho[0] + rho[1], 1e-30)
+        vols.append(float((frac > 0.9).sum()) / D ** 3)
+    lo, hi = THETA3[nominal]
+    bo0 = np.array([yl.bond_critical_tube(0.5 * (lo + hi), v) for v in vols])
+    bo1 = np.array([yl.bond_critical_tube_range(lo, hi, v) for v in vols])
+    print(wet, "V/D^3", np.round(vols, 2), "Bo_YL dtheta=0", np.round(bo0, 3),
+          "dtheta!=0", np.round(bo1, 3), flush=True)
+    bis = b3.lbm3d_critical_pressure(
+        [b3.cp3_problem(cfgs[0], 0.5 * to_g, 3.0 * to_g, sig, rho_bar, 40000, 160000,
+                        min_steps=20000)],
+        binding.cp_options(rel_tol=0.03, chunk_steps=1000, verify_bracket=1))[0]
+    start = max(0.02, round(bis["bo_crit"] / 0.02) * 0.02 - 0.1)
+    probs = [b3.cp3_problem(c, start * to_g, (start + 0.4) * to_g, sig, rho_bar, 40000,
+                            160000) for c in cfgs]
+    res = b3.lbm3d_critical_pressure(
+        probs, binding.cp_options(protocol="ramp", ramp_dg=0.02 * to_g, ramp_steps=40000,
+                                  chunk_steps=1000))
+    bos = np.array([r["bo_crit"] for r in res])
+    ratio = bos / bo0
+    print(wet, "slug lengths", [c["init"]["length"] for c in cfgs], "bisection Bo",
+          round(bis["bo_crit"], 3), "ramp Bo", np.round(bos, 3), "ratio", np.round(ratio, 3),
+          "ratio (dtheta!=0)", np.round(bos / bo1, 3), "flags", [r["flags"] for r in res])
+    assert all(r["flags"] & ~1 == 0 for r in res)
+    assert ratio.max() - ratio.min() <= spread
+    assert np.all(np.abs(ratio - 1) <= 0.2)
