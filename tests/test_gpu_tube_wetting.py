@@ -4,6 +4,8 @@ from the lattice (the 3-D counterpart of Table 1), and the critical Bond
 number of water-wet and oil-wet slugs in the paper's tube at four initial
 positions against the axisymmetric Young-Laplace estimate without and with
 that spread (Table 3 analogue)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +17,11 @@ pytestmark = pytest.mark.gpu
 NOMINAL = (30.0, 90.0, 150.0)
 # tube axis offsets (dy, dz) from the lattice, in lattice spacings
 OFFSETS = ((0.0, 0.0), (0.5, 0.0), (0.5, 0.5), (0.25, 0.25), (0.25, 0.0))
+
+
+# The resolution and viscosity studies take several minutes of GPU time each.
+studies = pytest.mark.skipif(os.environ.get("LBM_STUDIES") != "1",
+                             reason="long physics study; set LBM_STUDIES=1 to run it")
 
 
 def _straight_tube(r, theta, dy, dz, nx=112, length=56):
@@ -40,17 +47,13 @@ def _tube_angle(sim, cfg, axis):
     return 0.5 * (f + r), f, r
 
 
-def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
-    """Slugs at rest in straight tubes of radius 8 (the paper's neck radius)
-    after 30,000 steps, tau = 1: the angle of each wall-potential pair for
-    five axis offsets.  The map must stay symmetric about 90 deg and the
-    spread over the offsets (the lattice-orientation variation the paper's
-    fifth column accounts for) is reported."""
+def _angle_study(radius):
     from paper_1601_00918_amd.binding3d import Simulation3D
     res = {}
+    nx = int(14 * radius)
     for th in NOMINAL:
         for off in OFFSETS:
-            cfg, axis = _straight_tube(8.0, th, *off)
+            cfg, axis = _straight_tube(radius, th, *off, nx=nx, length=nx // 2)
             sim = Simulation3D(cfg)
             sim.step(30000)
             res[th, off] = _tube_angle(sim, cfg, axis)
@@ -58,7 +61,7 @@ def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
                   % ((th, str(off)) + res[th, off]), flush=True)
     for th in NOMINAL:
         vals = [res[th, o][0] for o in OFFSETS]
-        print("nominal %5.1f: %.2f - %.2f" % (th, min(vals), max(vals)))
+        print("radius %g nominal %5.1f: %.2f - %.2f" % (radius, th, min(vals), max(vals)))
     for o in OFFSETS:
         assert abs(res[90.0, o][0] - 90.0) <= 1.0
         assert abs(res[30.0, o][0] + res[150.0, o][0] - 180.0) <= 1.0
@@ -67,35 +70,54 @@ def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
         assert max(vals) - min(vals) <= 8.0
 
 
-# 3-D contact angles of the nominal 30 / 150 deg potentials in straight tubes
-# of radius 8 over the five axis offsets (measured by the test above).
-THETA3 = {30.0: (40.12, 40.55), 150.0: (139.45, 139.88)}
+def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
+    """Slugs at rest in straight tubes of radius 8 (the paper's neck radius)
+    after 30,000 steps, tau = 1: the angle of each wall-potential pair for
+    five axis offsets.  The map must stay symmetric about 90 deg and the
+    spread over the offsets (the lattice-orientation variation the paper's
+    fifth column accounts for) is reported."""
+    _angle_study(8.0)
 
 
-@pytest.mark.parametrize("wet,nominal,target,spread", [("water-wet", 30.0, 56.0, 0.08),
-                                                       ("oil-wet", 150.0, 69.0, 0.03)])
-def test_paper_tube_wettability_four_positions(gpu_available, wet, nominal, target, spread):
-    """Table 3 analogue: the paper's tube at D = 8 (three periods over L = 18 D,
-    radius D at the neck, 2.5 D at the widest), tau = 1, a water-wet (about
-    40 deg) or oil-wet (about 140 deg) wall, slugs of about the volume Table 2
-    targets (56 and 69 D^3) at four positions a quarter wavelength apart;
-    40,000 unforced steps, the 90 % volume rule, then the ramp of Delta Bo =
-    0.02 every 40,000 steps.  The critical Bo is compared with the axisymmetric
-    Young-Laplace value for the measured angle and volume (Delta theta = 0)
-    and with the highest value over the angle spread of the axis offsets
-    (Delta theta != 0).  The ratio to the analytic value must lie within 20 %
-    (the neutral case of the same tube sits at 0.85) and not depend on the
-    position beyond 0.03 (oil-wet) or 0.08 (water-wet: there the first
-    position mobilises one level in three lower, 0.06 in Bo, as the paper
-    notes for its water-wet slugs)."""
+@studies
+@pytest.mark.parametrize("radius", [6.0, 12.0])
+def test_tube_contact_angle_at_other_resolutions(gpu_available, radius):
+    """The same study in tubes of radius 6 and 12 (the paper's other neck
+    radii, Table 4)."""
+    _angle_study(radius)
+
+
+def _angle_range(radius, nominal):
+    """Range of the 3-D contact angle of one wall-potential pair over the axis
+    offsets, in straight tubes of the given radius."""
+    from paper_1601_00918_amd.binding3d import Simulation3D
+    vals = []
+    nx = int(14 * radius)
+    for off in OFFSETS:
+        cfg, axis = _straight_tube(radius, nominal, *off, nx=nx, length=nx // 2)
+        sim = Simulation3D(cfg)
+        sim.step(30000)
+        vals.append(_tube_angle(sim, cfg, axis)[0])
+    return min(vals), max(vals)
+
+
+def _paper_tube_study(D, nominal, target, tau=(1.0, 1.0), label=""):
+    """The paper's tube at neck radius D (three periods over L = 18 D, radius D
+    at the neck and 2.5 D at the widest), slugs of about `target` D^3 at four
+    positions a quarter wavelength apart; 40,000 unforced steps, the 90 %
+    volume rule, then the ramp of Delta Bo = 0.02 every 40,000 steps, started
+    0.1 below a coarse bisection on the first position.  Returns the measured
+    volumes, the critical Bo and the Young-Laplace values without and with the
+    angle spread, with the measured 3-D angle range of the wall potentials."""
     from oracle import young_laplace as yl
     from paper_1601_00918_amd import binding, binding3d as b3
-    D, sig, rho_bar = 8, 0.195, 1.03
-    base = dict(lam=48, r0=14.0, a=6.0, nx=144, theta=nominal, tau=(1.0, 1.0))
+    sig, rho_bar = 0.195, 1.03
+    lam = 6 * D
+    base = dict(lam=lam, r0=1.75 * D, a=0.75 * D, nx=18 * D, theta=nominal, tau=tau)
     col = synth.mask3_of(synth.config_tube(**base)).sum(axis=(0, 1))
     cfgs = []
     for j in range(4):
-        x0 = 4 + 12 * j
+        x0 = D // 2 + (lam // 4) * j
         n = int(np.searchsorted(np.cumsum(np.roll(col, -x0)), target * D ** 3)) + 1
         cfgs.append(synth.config_tube(slug_x0=x0, slug_len=n, **base))
     L = cfgs[0]["nx"]
@@ -107,11 +129,9 @@ def test_paper_tube_wettability_four_positions(gpu_available, wet, nominal, targ
         rho = sim.moments()["rho"]
         frac = rho[0] / np.maximum(rho[0] + rho[1], 1e-30)
         vols.append(float((frac > 0.9).sum()) / D ** 3)
-    lo, hi = THETA3[nominal]
+    lo, hi = (90.0, 90.0) if nominal == 90.0 else _angle_range(float(D), nominal)
     bo0 = np.array([yl.bond_critical_tube(0.5 * (lo + hi), v) for v in vols])
     bo1 = np.array([yl.bond_critical_tube_range(lo, hi, v) for v in vols])
-    print(wet, "V/D^3", np.round(vols, 2), "Bo_YL dtheta=0", np.round(bo0, 3),
-          "dtheta!=0", np.round(bo1, 3), flush=True)
     bis = b3.lbm3d_critical_pressure(
         [b3.cp3_problem(cfgs[0], 0.5 * to_g, 3.0 * to_g, sig, rho_bar, 40000, 160000,
                         min_steps=20000)],
@@ -123,10 +143,58 @@ def test_paper_tube_wettability_four_positions(gpu_available, wet, nominal, targ
         probs, binding.cp_options(protocol="ramp", ramp_dg=0.02 * to_g, ramp_steps=40000,
                                   chunk_steps=1000))
     bos = np.array([r["bo_crit"] for r in res])
-    ratio = bos / bo0
-    print(wet, "slug lengths", [c["init"]["length"] for c in cfgs], "bisection Bo",
-          round(bis["bo_crit"], 3), "ramp Bo", np.round(bos, 3), "ratio", np.round(ratio, 3),
-          "ratio (dtheta!=0)", np.round(bos / bo1, 3), "flags", [r["flags"] for r in res])
-    assert all(r["flags"] & ~1 == 0 for r in res)
+    print("%s D=%d nominal %g tau %s: theta3 %.2f-%.2f slug lengths %s V/D^3 %s Bo %s "
+          "Bo_YL(dtheta=0) %s Bo_YL(dtheta!=0) %s ratio %s flags %s"
+          % (label, D, nominal, tau, lo, hi, [c["init"]["length"] for c in cfgs],
+             np.round(vols, 2), np.round(bos, 3), np.round(bo0, 3), np.round(bo1, 3),
+             np.round(bos / bo0, 3), [r["flags"] for r in res]), flush=True)
+    return dict(vols=np.array(vols), bo=bos, bo0=bo0, bo1=bo1, flags=[r["flags"] for r in res])
+
+
+@pytest.mark.parametrize("wet,nominal,target,spread", [("water-wet", 30.0, 56.0, 0.08),
+                                                       ("oil-wet", 150.0, 69.0, 0.03)])
+def test_paper_tube_wettability_four_positions(gpu_available, wet, nominal, target, spread):
+    """Table 3 analogue: the paper's tube at D = 8, tau = 1, a water-wet (about
+    40 deg) or oil-wet (about 140 deg) wall, slugs of about the volume Table 2
+    targets (56 and 69 D^3) at four positions.  The critical Bo is compared
+    with the axisymmetric Young-Laplace value for the measured angle and
+    volume (Delta theta = 0) and with the highest value over the angle spread
+    of the axis offsets (Delta theta != 0).  The ratio to the analytic value
+    must lie within 20 % (the neutral case of the same tube sits at 0.85) and
+    not depend on the position beyond 0.03 (oil-wet) or 0.08 (water-wet:
+    there the first position mobilises one level in three lower, 0.06 in Bo,
+    as the paper notes for its water-wet slugs)."""
+    r = _paper_tube_study(8, nominal, target, label=wet)
+    ratio = r["bo"] / r["bo0"]
+    assert all(f & ~1 == 0 for f in r["flags"])
     assert ratio.max() - ratio.min() <= spread
     assert np.all(np.abs(ratio - 1) <= 0.2)
+
+
+@studies
+@pytest.mark.parametrize("D", [6, 12])
+@pytest.mark.parametrize("wet,nominal,target", [("intermediate", 90.0, 58.0),
+                                                ("water-wet", 30.0, 56.0),
+                                                ("oil-wet", 150.0, 69.0)])
+def test_paper_tube_resolution_study(gpu_available, D, wet, nominal, target):
+    """Table 4 analogue: the same study at neck radii D = 6 and 12."""
+    r = _paper_tube_study(D, nominal, target, label=wet)
+    assert all(f & ~1 == 0 for f in r["flags"])
+    assert np.all(np.abs(r["bo"] / r["bo0"] - 1) <= 0.25)
+
+
+@studies
+@pytest.mark.parametrize("wet,nominal,target,tau_w", [("intermediate", 90.0, 58.0, 0.6),
+                                                      ("water-wet", 30.0, 56.0, 0.55),
+                                                      ("oil-wet", 150.0, 69.0, 0.7)])
+def test_paper_tube_viscosity_ratio_study(gpu_available, wet, nominal, target, tau_w):
+    """Table 5 analogue: D = 8 with tau_o = 1.5 and a low tau_w (the paper's
+    0.55, oil 20 times more viscous than water).  The sharp initial slug at
+    tau_w = 0.55 diverges within 1,000 steps with the neutral and oil-wet
+    potentials (the water-wet case runs), so those two take the lowest tau_w
+    that runs: 0.6 (viscosity ratio 10) and 0.7 (ratio 5).  The quasi-static
+    critical Bo does not depend on the viscosities; the ratio to the analytic
+    value must stay within 25 %."""
+    r = _paper_tube_study(8, nominal, target, tau=(1.5, tau_w), label=wet)
+    assert all(f & ~1 == 0 for f in r["flags"])
+    assert np.all(np.abs(r["bo"] / r["bo0"] - 1) <= 0.25)
