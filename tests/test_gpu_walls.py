@@ -19,7 +19,7 @@ def _oracle(cfg):
     yc = 0.5 * (cfg["ny"] - 1) + cfg.get("y_offset", 0.0)
     wall = (yc, cfg["h0"], cfg["a"], cfg["lam"]) if cfg.get("wall_interp") else None
     p = orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"],
-                   g=cfg["g"], wall=wall)
+                   g=cfg["g"], wall=wall, reg_order=cfg.get("reg_order", 2))
     return orc.Lattice(p, mask, synth.rho0_of(cfg, mask)), mask
 
 
@@ -27,10 +27,11 @@ def _cases():
     ch = dict(synth.config_channel(lam=64, theta=120.0, g=1e-5, tau=(0.8, 1.2)), wall_interp=1)
     return {"plates0.2": dict(synth.config_plates(16, theta=60.0, offset=0.2), g=(2e-6, 0.0)),
             "plates0.7": synth.config_plates(16, theta=140.0, offset=0.7),
-            "channel": ch}
+            "channel": ch,
+            "channel-reg3": dict(ch, reg_order=3)}
 
 
-@pytest.mark.parametrize("which", ["plates0.2", "plates0.7", "channel"])
+@pytest.mark.parametrize("which", ["plates0.2", "plates0.7", "channel", "channel-reg3"])
 def test_few_steps_and_1000_steps_match_oracle(gpu_available, which):
     from paper_1601_00918_amd import Simulation
     cfg = _cases()[which]
