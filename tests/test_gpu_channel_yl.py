@@ -1,0 +1,73 @@
+"""Critical pressure of the D2Q9 sinusoidal channel (Sec. 3.4 in two
+dimensions) against the quasi-static planar Young-Laplace estimate, over the
+contact angles of the wall-potential map and two resolutions (lambda = 128 and
+256 with h0 = lambda / 8, a = lambda / 16: neck half-widths 8 and 16)."""
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import synth
+from oracle import young_laplace as yl
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 0.161   # surface tension of the D2Q9 model at G = -2.7 (Laplace fit)
+RHO_BAR = 1.03
+# contact angle (through water) each nominal wall-potential pair gives between
+# plates, measured with the Sec. 3.3 detection (H = 16 .. 64 agree within 0.6 deg)
+THETA2 = {30.0: 42.0, 60.0: 65.5, 90.0: 90.0, 120.0: 114.5, 150.0: 138.0}
+
+
+def _area_after(cfg, steps):
+    """Slug area after the unforced equilibration (nodes whose oil fraction
+    exceeds 0.9)."""
+    from paper_1601_00918_amd import Simulation
+    sim = Simulation([cfg])
+    sim.step(steps)
+    rho = sim.moments(0)["rho"]
+    return float((rho[0] / np.maximum(rho[0] + rho[1], 1e-30) > 0.9).sum())
+
+
+@pytest.mark.parametrize("lam", [128, pytest.param(256, marks=pytest.mark.skipif(
+    os.environ.get("LBM_STUDIES") != "1", reason="long study; set LBM_STUDIES=1 to run it"))])
+def test_channel_critical_pressure_vs_planar_young_laplace(gpu_available, lam):
+    """Bisection to 1 %.  A water-wet slug forced below its threshold first
+    hops most of a wavelength (0.86 lambda at lambda = 128) to a new rest
+    position, so a probe counts as moving only after 1.5 lambda and as static
+    below 1.25 lambda.  The model holds the slug beyond the quasi-static
+    maximum: the critical forcing is 1.0-1.9 times the Young-Laplace value,
+    as if the contact angle could vary by +-6-11 deg (contact-line pinning on
+    the staircase wall potentials; the paper reports the same direction of
+    deviation).  The test bounds the ratio to [0.95, 2.0] and prints the
+    equivalent angle range."""
+    from paper_1601_00918_amd import binding
+    equil = 20000 if lam == 128 else 40000
+    budget = 300000 if lam == 128 else 500000
+    cfgs, g_yl = [], []
+    for nominal, th in THETA2.items():
+        cfg = synth.config_channel(lam=lam, theta=nominal)
+        area = _area_after(cfg, equil)
+        dps, _ = yl.bond_critical_channel(lam, cfg["h0"], cfg["a"], th, area)
+        g_yl.append(dps * SIGMA / (RHO_BAR * cfg["nx"]))
+        cfgs.append((cfg, area))
+    probs = [binding.cp_problem(c, 0.5 * g, 3.0 * g, SIGMA, RHO_BAR, equil, budget)
+             for (c, _), g in zip(cfgs, g_yl)]
+    res = binding.lbm_critical_pressure(
+        probs, binding.cp_options(rel_tol=0.01, chunk_steps=500, verify_bracket=1,
+                                  move_frac=1.5, creep_frac=1.25))
+    ratio = np.array([r["g_crit"] / g for r, g in zip(res, g_yl)])
+    for (c, area), r, g, q in zip(cfgs, res, g_yl, ratio):
+        th = THETA2[c["theta"]]
+        ch = yl.Channel(c["h0"], c["a"], lam, axisymmetric=False)
+
+        def excess(d):
+            dp, _ = yl.critical_pressure_range(ch, th - d, th + d, area, n_scan=121)
+            return dp * SIGMA / (RHO_BAR * c["nx"]) - r["g_crit"]
+        d = brentq(excess, 0.0, 40.0, xtol=0.05) if q > 1.0 else 0.0
+        print("lambda %d theta %.1f area %.0f g_YL %.4e g_LBM %.4e ratio %.3f flags %d "
+              "equivalent angle range +-%.1f deg" % (lam, th, area, g, r["g_crit"], q,
+                                                     r["flags"], d), flush=True)
+    assert all(r["flags"] == 0 for r in res)
+    assert np.all(ratio >= 0.95) and np.all(ratio <= 2.0)
