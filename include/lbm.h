@@ -106,6 +106,8 @@ typedef struct {
 } lbm_fluid;
 
 /* Initial densities; populations start at rest equilibrium f_i = w_i rho0. */
+#define LBM_MAX_SLUGS 8 /* slugs of one SLUG initial state */
+
 typedef enum {
     LBM_INIT_UNIFORM = 0, /* rho0 = (rho_hi, rho_lo) everywhere */
     LBM_INIT_DROPLET = 1, /* oil rho_hi inside the disc of radius r around (cx, cy)
@@ -114,7 +116,9 @@ typedef enum {
                              species 1 - core_species at rho_hi, the rest species
                              core_species at rho_hi; the other species rho_lo */
     LBM_INIT_SLUG = 3,    /* oil rho_hi at fluid nodes with (x - x0) mod nx < length,
-                             water elsewhere; the other species rho_lo */
+                             water elsewhere; the other species rho_lo.  With
+                             n_slugs >= 1: oil in every slug (x0_k, length_k) of
+                             `slugs` (several slugs in series) */
     LBM_INIT_FIELD = 4    /* explicit host field rho0 [2][ny][nx]: reserved, currently
                              rejected with LBM_ERR_UNSUPPORTED */
 } lbm_init_kind;
@@ -123,11 +127,15 @@ typedef struct {
     int32_t kind;        /* lbm_init_kind */
     int32_t wall_rows;   /* LAYERS */
     int32_t core_species;/* LAYERS */
-    int32_t reserved;
+    int32_t n_slugs;     /* SLUG: 0 = the slug (x0, length); 1..LBM_MAX_SLUGS = that
+                            many slugs, given in `slugs` */
     double rho_hi, rho_lo;
     double cx, cy, r;    /* DROPLET */
     double x0, length;   /* SLUG */
     const double* rho0;  /* FIELD (reserved), [2][ny][nx] */
+    const double* slugs; /* SLUG with n_slugs >= 1: host [n_slugs][2] pairs
+                            (x0, length), length >= 0, read during lbm_init;
+                            LBM_ERR_INVALID if null or out of range */
 } lbm_init_fields;
 
 /* Population storage format in HBM (arithmetic is always FP32).  The storage

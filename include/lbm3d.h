@@ -68,15 +68,17 @@ typedef enum {
     LBM3D_INIT_DROPLET = 1, /* oil rho_hi inside the ball of radius r around (cx, cy, cz)
                                (periodic distance, strict <), rho_lo outside; water mirrored */
     LBM3D_INIT_SLUG = 3     /* oil rho_hi at fluid nodes with (x - x0) mod nx < length,
-                               water elsewhere; the other species rho_lo */
+                               water elsewhere; the other species rho_lo; with
+                               n_slugs >= 1 every slug of `slugs` (as in lbm.h) */
 } lbm3d_init_kind;
 
 typedef struct {
     int32_t kind;         /* lbm3d_init_kind */
-    int32_t reserved;
+    int32_t n_slugs;      /* SLUG: 0 = (x0, length); 1..LBM_MAX_SLUGS: `slugs` */
     double rho_hi, rho_lo;
     double cx, cy, cz, r; /* DROPLET */
     double x0, length;    /* SLUG */
+    const double* slugs;  /* SLUG, n_slugs >= 1: host [n_slugs][2] (x0, length) */
 } lbm3d_init_fields;
 
 typedef struct lbm3d_ctx lbm3d_ctx;

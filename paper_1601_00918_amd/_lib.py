@@ -38,6 +38,7 @@ INIT3_UNIFORM, INIT3_DROPLET, INIT3_SLUG = 0, 1, 3
 
 OPT_SNAPSHOT = 0x100
 CP_UNDECIDED, CP_UNSTABLE, CP_WIDENED, CP_NOT_CONVERGED = 1, 2, 4, 8
+MAX_SLUGS = 8
 CP_BISECT, CP_RAMP = 0, 1
 
 
@@ -62,11 +63,12 @@ class LbmFluid(ctypes.Structure):
 
 class LbmInitFields(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("wall_rows", ctypes.c_int32),
-                ("core_species", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("core_species", ctypes.c_int32), ("n_slugs", ctypes.c_int32),
                 ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("r", ctypes.c_double),
                 ("x0", ctypes.c_double), ("length", ctypes.c_double),
-                ("rho0", ctypes.POINTER(ctypes.c_double))]
+                ("rho0", ctypes.POINTER(ctypes.c_double)),
+                ("slugs", ctypes.POINTER(ctypes.c_double))]
 
 
 class LbmMonitor(ctypes.Structure):
@@ -113,10 +115,11 @@ class Lbm3dFluid(ctypes.Structure):
 
 
 class Lbm3dInitFields(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("kind", ctypes.c_int32), ("n_slugs", ctypes.c_int32),
                 ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double),
-                ("r", ctypes.c_double), ("x0", ctypes.c_double), ("length", ctypes.c_double)]
+                ("r", ctypes.c_double), ("x0", ctypes.c_double), ("length", ctypes.c_double),
+                ("slugs", ctypes.POINTER(ctypes.c_double))]
 
 
 class Lbm3dCpProblem(ctypes.Structure):

@@ -53,7 +53,8 @@ def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0), reg_order=2):
 
 
 def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=0,
-                core_species=0, x0=0.0, length=0.0, rho0=None, _keep=None):
+                core_species=0, x0=0.0, length=0.0, rho0=None, slugs=None, _keep=None):
+    """slugs: optional list of (x0, length) pairs (several slugs in series)."""
     s = LbmInitFields()
     s.kind = _INIT_KINDS[kind] if isinstance(kind, str) else int(kind)
     s.rho_hi, s.rho_lo = float(rho_hi), float(rho_lo)
@@ -65,6 +66,13 @@ def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=
         if _keep is not None:
             _keep.append(a)
         s.rho0 = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if slugs is not None:
+        a = np.ascontiguousarray(slugs, dtype=np.float64).reshape(-1, 2)
+        s.n_slugs = a.shape[0]
+        s.slugs = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s._slugs = a
+        if _keep is not None:
+            _keep.append(a)
     return s
 
 
@@ -81,7 +89,7 @@ def structs_from_config(cfg, rho0=None, keep=None):
     else:
         ini = dict(cfg["init"])
         kind = ini.pop("kind")
-        init = init_struct(kind, **ini)
+        init = init_struct(kind, _keep=keep, **ini)
     return geom, fluid, init
 
 
@@ -233,9 +241,11 @@ def cp_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, keep=Non
                min_steps=0):
     """Critical-pressure problem from a channel workload dict (min_steps 0:
     the options' value)."""
+    keep = [] if keep is None else keep  # host arrays the structs point to
     g, f, i = structs_from_config(cfg, None, keep)
     p = LbmCpProblem()
     p.geom, p.fluid, p.init = g, f, i
+    p._keep = keep
     p.sigma, p.rho_bar = float(sigma), float(rho_bar)
     p.g_lo, p.g_hi = float(g_lo), float(g_hi)
     p.equil_steps, p.max_steps = int(equil_steps), int(max_steps)

@@ -41,12 +41,20 @@ def fluid3_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0, 0.0)):
 
 
 def init3_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, cz=0.0, r=0.0, x0=0.0,
-                 length=0.0):
+                 length=0.0, slugs=None, _keep=None):
+    """slugs: optional list of (x0, length) pairs (several slugs in series)."""
     s = Lbm3dInitFields()
     s.kind = _INIT_KINDS[kind] if isinstance(kind, str) else int(kind)
     s.rho_hi, s.rho_lo = float(rho_hi), float(rho_lo)
     s.cx, s.cy, s.cz, s.r = float(cx), float(cy), float(cz), float(r)
     s.x0, s.length = float(x0), float(length)
+    if slugs is not None:
+        a = np.ascontiguousarray(slugs, dtype=np.float64).reshape(-1, 2)
+        s.n_slugs = a.shape[0]
+        s.slugs = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s._slugs = a
+        if _keep is not None:
+            _keep.append(a)
     return s
 
 
@@ -63,7 +71,7 @@ def structs3_from_config(cfg, keep=None, rho_hi=None, rho_lo=None):
         ini["rho_hi"] = rho_hi
     if rho_lo is not None:
         ini["rho_lo"] = rho_lo
-    init = init3_struct(ikind, **ini)
+    init = init3_struct(ikind, _keep=keep, **ini)
     return geom, fluid, init
 
 
@@ -164,9 +172,11 @@ def lbm3d_destroy(ctx):
 
 def cp3_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, min_steps=0):
     """Tube critical-pressure problem from a tube workload dict."""
-    g, f, i = structs3_from_config(cfg)
+    keep = []  # host arrays the structs point to, alive as long as the problem
+    g, f, i = structs3_from_config(cfg, keep)
     p = Lbm3dCpProblem()
     p.geom, p.fluid, p.init = g, f, i
+    p._keep = keep
     p.sigma, p.rho_bar = float(sigma), float(rho_bar)
     p.g_lo, p.g_hi = float(g_lo), float(g_hi)
     p.equil_steps, p.max_steps = int(equil_steps), int(max_steps)

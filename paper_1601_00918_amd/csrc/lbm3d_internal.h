@@ -2,6 +2,8 @@
 // their host runtime (lbm3d_runtime.cpp).  Not part of the public ABI.
 #pragma once
 
+#include "lbm.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -46,10 +48,10 @@ constexpr int kMon3Width = 8;
 // Initial state (one launch).
 struct Init3Dev {
     int32_t kind;  // 0 uniform, 1 droplet (sphere), 3 slug
-    int32_t pad;
+    int32_t n_slugs;  // slug: slugs in x0 / length (>= 1)
     double rho_hi, rho_lo;
     double cx, cy, cz, r;
-    double x0, length;
+    double x0[LBM_MAX_SLUGS], length[LBM_MAX_SLUGS];
 };
 
 // Supported workgroup tiles (inner nodes per item in x and y).

@@ -556,11 +556,14 @@ __device__ double init_density3(const Init3Dev& ini, const Inst3Dev& P, int s, i
         oil = (dx * dx + dy * dy + dz * dz) < ini.r * ini.r;
         break;
     }
-    default: {  // slug: (x - x0) mod nx < length
-        double rel = fmod((double)x - ini.x0, (double)P.nx);
-        if (rel < 0.0)
-            rel += (double)P.nx;
-        oil = rel < ini.length;
+    default: {  // slugs: (x - x0_k) mod nx < length_k for some k
+        oil = false;
+        for (int k = 0; k < ini.n_slugs; ++k) {
+            double rel = fmod((double)x - ini.x0[k], (double)P.nx);
+            if (rel < 0.0)
+                rel += (double)P.nx;
+            oil = oil || rel < ini.length[k];
+        }
         break;
     }
     }

@@ -381,6 +381,14 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     if (init->kind != LBM3D_INIT_UNIFORM && init->kind != LBM3D_INIT_DROPLET &&
         init->kind != LBM3D_INIT_SLUG)
         return fail(LBM_ERR_INVALID, "lbm3d_init: unknown init kind %d", init->kind);
+    double slug_x0[LBM_MAX_SLUGS], slug_len[LBM_MAX_SLUGS];
+    int32_t n_slugs = 1;
+    if (init->kind == LBM3D_INIT_SLUG) {
+        std::string err;
+        if (!lbm::slug_list(init->n_slugs, init->slugs, init->x0, init->length, slug_x0,
+                            slug_len, n_slugs, err))
+            return fail(LBM_ERR_INVALID, "lbm3d_init: %s", err.c_str());
+    }
     if (!(init->rho_hi > 0.0) || !(init->rho_lo > 0.0) ||
         !std::isfinite(init->rho_hi + init->rho_lo))
         return fail(LBM_ERR_INVALID, "lbm3d_init: densities must be finite and > 0");
@@ -441,8 +449,11 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     ini.cy = init->cy;
     ini.cz = init->cz;
     ini.r = init->r;
-    ini.x0 = init->x0;
-    ini.length = init->length;
+    ini.n_slugs = n_slugs;
+    for (int k = 0; k < n_slugs; ++k) {
+        ini.x0[k] = init->kind == LBM3D_INIT_SLUG ? slug_x0[k] : init->x0;
+        ini.length[k] = init->kind == LBM3D_INIT_SLUG ? slug_len[k] : init->length;
+    }
     e = launch3_init(fmt, c->buf[0], c->P, c->runs_d, ini, c->stream);
     if (e != hipSuccess)
         return hip_bail(e, "init kernel launch");

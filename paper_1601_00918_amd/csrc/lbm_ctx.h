@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,31 @@ struct Layout {
     int64_t max_nodes;
 };
 
+
+// Slugs of a SLUG initial state: the single (x0, length) when n is 0, else the
+// n host pairs.  Returns false with a message on invalid input.
+inline bool slug_list(int32_t n, const double* pairs, double x0, double length, double* xs,
+                      double* ls, int32_t& count, std::string& err)
+{
+    if (n < 0 || n > LBM_MAX_SLUGS) {
+        err = "n_slugs must lie in 0.." + std::to_string(LBM_MAX_SLUGS);
+        return false;
+    }
+    if (n >= 1 && !pairs) {
+        err = "n_slugs >= 1 needs the slugs array";
+        return false;
+    }
+    count = n == 0 ? 1 : n;
+    for (int k = 0; k < count; ++k) {
+        xs[k] = n == 0 ? x0 : pairs[2 * k];
+        ls[k] = n == 0 ? length : pairs[2 * k + 1];
+        if (!std::isfinite(xs[k]) || !(ls[k] >= 0.0) || !std::isfinite(ls[k])) {
+            err = "slug " + std::to_string(k) + ": x0 must be finite and length >= 0";
+            return false;
+        }
+    }
+    return true;
+}
 
 }  // namespace lbm
 

@@ -58,6 +58,23 @@ double wrap_half(double d, double nx)
     return d;
 }
 
+// Probes follow the periodic centre of oil mass through the first Fourier
+// mode of the oil density along x.  Identical slugs spaced evenly around the
+// domain cancel that mode, and their motion cannot be followed.
+lbm_status check_trackable(const std::vector<lbm_monitor>& mon)
+{
+    for (size_t k = 0; k < mon.size(); ++k) {
+        const double amp = std::hypot(mon[k].oil_cos, mon[k].oil_sin);
+        if (!(amp > 0.01 * mon[k].mass[0]))
+            return fail(LBM_ERR_UNSUPPORTED,
+                        "problem %d: the oil density has no first Fourier mode along x "
+                        "(slugs spaced evenly around the domain?), so the slug cannot be "
+                        "tracked",
+                        (int)k);
+    }
+    return LBM_OK;
+}
+
 lbm_status check_problem(const lbm_cp_problem& p, int k)
 {
     if (p.geom.kind != LBM_GEOM_CHANNEL)
@@ -130,6 +147,8 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
     std::vector<lbm_monitor> mon(n);
     lbm_status e = eng.monitors(mon);
     if (e != LBM_OK)
+        return e;
+    if ((e = check_trackable(mon)) != LBM_OK)
         return e;
     std::vector<double> xc0(n);
     for (int k = 0; k < n; ++k) {
@@ -295,6 +314,8 @@ lbm_status ramp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm
     std::vector<lbm_monitor> mon(n);
     lbm_status e = eng.monitors(mon);
     if (e != LBM_OK)
+        return e;
+    if ((e = check_trackable(mon)) != LBM_OK)
         return e;
     for (int k = 0; k < n; ++k) {
         std::memset(&res[k], 0, sizeof(lbm_cp_result));

@@ -2,6 +2,8 @@
 // host runtime (lbm_runtime.cpp).  Not part of the public ABI.
 #pragma once
 
+#include "lbm.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -63,10 +65,10 @@ struct InitDev {
     int32_t core_species;
     int32_t first_row, last_row;   // LAYERS: first / last fluid row of the box
     int32_t wall_rows;
-    int32_t pad;
+    int32_t n_slugs;               // SLUG: slugs in x0 / length (>= 1)
     double rho_hi, rho_lo;
     double cx, cy, r;
-    double x0, length;
+    double x0[LBM_MAX_SLUGS], length[LBM_MAX_SLUGS];
 };
 
 // Export staging layout (doubles, one instance): [23][ny*nx]

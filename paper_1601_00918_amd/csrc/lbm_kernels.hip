@@ -753,11 +753,15 @@ __device__ double init_density(const InitDev& ini, const InstDev& P, int s, int 
         const bool in_core_species = (s == ini.core_species);
         return (core == in_core_species) ? ini.rho_hi : ini.rho_lo;
     }
-    default: {  // slug
-        double rel = fmod((double)x - ini.x0, (double)P.nx);
-        if (rel < 0.0)
-            rel += (double)P.nx;
-        oil = rel < ini.length ? 1.0 : 0.0;
+    default: {  // slugs: (x - x0_k) mod nx < length_k for some k
+        oil = 0.0;
+        for (int k = 0; k < ini.n_slugs; ++k) {
+            double rel = fmod((double)x - ini.x0[k], (double)P.nx);
+            if (rel < 0.0)
+                rel += (double)P.nx;
+            if (rel < ini.length[k])
+                oil = 1.0;
+        }
         break;
     }
     }

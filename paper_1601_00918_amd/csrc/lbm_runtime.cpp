@@ -509,6 +509,13 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
             return fail(LBM_ERR_INVALID, "instance %d: rho_hi, rho_lo must be > 0", k);
         if (in.kind == LBM_INIT_LAYERS && (in.core_species < 0 || in.core_species > 1))
             return fail(LBM_ERR_INVALID, "instance %d: core_species must be 0 or 1", k);
+        if (in.kind == LBM_INIT_SLUG) {
+            double xs[LBM_MAX_SLUGS], ls[LBM_MAX_SLUGS];
+            int32_t cnt = 0;
+            std::string err;
+            if (!slug_list(in.n_slugs, in.slugs, in.x0, in.length, xs, ls, cnt, err))
+                return fail(LBM_ERR_INVALID, "instance %d: %s", k, err.c_str());
+        }
     }
     const Layout L = layout_of(geoms, n_inst, storage);
     if (workspace_bytes < L.total)
@@ -634,8 +641,11 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         ini.cx = in.cx;
         ini.cy = in.cy;
         ini.r = in.r;
-        ini.x0 = in.x0;
-        ini.length = in.length;
+        {
+            std::string err;  // validated above
+            (void)slug_list(in.n_slugs, in.slugs, in.x0, in.length, ini.x0, ini.length,
+                            ini.n_slugs, err);
+        }
         int first = h.ny, last = -1;
         for (const Col& cc : h.cols)
             if (cc.lo <= cc.hi) {

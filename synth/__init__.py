@@ -82,11 +82,13 @@ def layers_field(nx, ny, wall_rows, mask, core_species=0, hi=RHO_HI, lo=RHO_LO):
     return rho
 
 
-def slug_field(nx, ny, x0, length, mask, hi=RHO_HI, lo=RHO_LO):
-    """Oil slug: fluid nodes with x in [x0, x0 + length) (periodic) are oil."""
+def slug_field(nx, ny, x0, length, mask, hi=RHO_HI, lo=RHO_LO, slugs=None):
+    """Oil slug: fluid nodes with x in [x0, x0 + length) (periodic) are oil;
+    with slugs (a list of (x0, length) pairs) every listed slug is oil."""
     x = np.arange(nx)[None, :] * np.ones((ny, 1), dtype=np.int64)
-    rel = np.mod(x - x0, nx)
-    oil = rel < length
+    oil = np.zeros((ny, nx), dtype=bool)
+    for s0, sl in (slugs if slugs is not None else [(x0, length)]):
+        oil |= np.mod(x - s0, nx) < sl
     rho = np.empty((2, ny, nx))
     rho[0] = np.where(oil, hi, lo)
     rho[1] = np.where(oil, lo, hi)
@@ -230,7 +232,8 @@ def rho0_of(cfg, mask=None):
     if ini["kind"] == "layers":
         return layers_field(nx, ny, ini["wall_rows"], mask, ini.get("core_species", 0))
     if ini["kind"] == "slug":
-        return slug_field(nx, ny, ini["x0"], ini["length"], mask)
+        return slug_field(nx, ny, ini.get("x0", 0.0), ini.get("length", 0.0), mask,
+                          slugs=ini.get("slugs"))
     if ini["kind"] == "uniform":
         return np.stack([np.full((ny, nx), RHO_HI), np.full((ny, nx), RHO_LO)])
     raise ValueError(ini["kind"])
@@ -339,7 +342,9 @@ def rho03_of(cfg, mask=None):
                pd(z, ini["cz"], nz) ** 2) < ini["r"] ** 2
     elif ini["kind"] == "slug":
         x = np.arange(nx)[None, None, :] * np.ones((nz, ny, 1), dtype=np.int64)
-        oil = np.mod(x - ini["x0"], nx) < ini["length"]
+        oil = np.zeros(mask.shape, dtype=bool)
+        for s0, sl in ini.get("slugs") or [(ini["x0"], ini["length"])]:
+            oil |= np.mod(x - s0, nx) < sl
     else:
         raise ValueError(ini["kind"])
     rho = np.empty((2,) + mask.shape)

@@ -206,3 +206,28 @@ def test_interpolated_walls_validate_on_the_host():
         with pytest.raises(_lib.LbmError) as e:
             binding.lbm_init([g], fl, ini, storage, 1 << 20, 1 << 30, 0)
         assert e.value.status == status and text in str(e.value), (text, str(e.value))
+
+
+def test_multiple_slugs_validate_on_the_host():
+    """Rejected before any device work (the workspace pointer is never used)."""
+    from paper_1601_00918_amd import binding3d as b3
+    g = [_geom()]
+    fl = [binding.fluid_struct((1.0, 1.0), -2.7)]
+    bad = [binding.init_struct("slug", slugs=[(0.0, 10.0)] * 9),            # > LBM_MAX_SLUGS
+           binding.init_struct("slug", slugs=[(0.0, 10.0), (40.0, -1.0)]),  # negative length
+           binding.init_struct("slug", slugs=[(0.0, 10.0), (float("nan"), 5.0)])]
+    for ini in bad:
+        with pytest.raises(_lib.LbmError) as e:
+            _try_init(g, fl, [ini])
+        assert e.value.status == 1 and "slug" in str(e.value)
+    nul = binding.init_struct("slug")
+    nul.n_slugs = 1                                   # count without the array
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init(g, fl, [nul])
+    assert "slugs array" in str(e.value)
+    g3 = b3.geom3_struct("tube", 96, 18, 18, lam=32.0, r0=6.0, a=2.0)
+    f3 = b3.fluid3_struct((1.0, 1.0), -2.7)
+    i3 = b3.init3_struct("slug", slugs=[(0.0, 10.0)] * 9)
+    with pytest.raises(_lib.LbmError) as e:
+        b3.lbm3d_init(g3, f3, i3, "f32", 1 << 20, 1 << 30, 0)
+    assert e.value.status == 1 and "n_slugs" in str(e.value)

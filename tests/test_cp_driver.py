@@ -242,3 +242,23 @@ def test_ramp_carries_the_displacement_of_a_moving_slug():
     ref = odrv.ramp(RampEngine(plain, g_stars, creepers=[0]), plain, dg, 40000)[0]
     assert res["probes"] == ref["probes"] and res["g_crit"] == pytest.approx(ref["g_crit"])
     assert res["g_crit"] <= 0.8 * g_stars[0] + 6 * dg + 1e-18
+
+
+def test_slugs_without_a_first_fourier_mode_are_rejected():
+    """Identical slugs spaced evenly around the domain cancel the first Fourier
+    mode of the oil density that the probes track: both protocols refuse
+    them instead of following noise."""
+    probs, plain = _problems([1e-5])
+
+    class Even(RampEngine):
+        def monitors(self):
+            out = super().monitors()
+            for m in out:
+                m["oil_cos"], m["oil_sin"] = 1e-9, -2e-9
+            return out
+    for proto in ("bisect", "ramp"):
+        opts = binding.cp_options(protocol=proto, ramp_dg=1e-6, ramp_steps=1000,
+                                  chunk_steps=500)
+        with pytest.raises(binding._lib.LbmError) as e:
+            binding.lbm_cp_drive(Even(plain, [1e-5]), probs, opts)
+        assert e.value.status == 6 and "Fourier" in str(e.value)
