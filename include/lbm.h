@@ -50,7 +50,7 @@ typedef enum {
     LBM_ERR_OOM = 3,         /* workspace smaller than required */
     LBM_ERR_UNSTABLE = 4,    /* a density became non-finite or non-positive */
     LBM_ERR_BUDGET = 5,      /* step budget exhausted without a decision */
-    LBM_ERR_UNSUPPORTED = 6  /* valid request this build does not support */
+    LBM_ERR_UNSUPPORTED = 6  /* valid request the library does not support */
 } lbm_status;
 
 /* Geometry of one instance. */

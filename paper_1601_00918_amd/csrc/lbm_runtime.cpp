@@ -503,7 +503,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         if (in.kind == LBM_INIT_FIELD)
             return fail(LBM_ERR_UNSUPPORTED,
                         "instance %d: explicit initial fields (LBM_INIT_FIELD) are switched "
-                        "off in this build; use a preset", k);
+                        "off in this version of the library; use a preset", k);
         if (in.kind != LBM_INIT_FIELD &&
             (!(in.rho_hi > 0.0) || !(in.rho_lo > 0.0) || !std::isfinite(in.rho_hi + in.rho_lo)))
             return fail(LBM_ERR_INVALID, "instance %d: rho_hi, rho_lo must be > 0", k);
