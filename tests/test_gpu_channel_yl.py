@@ -30,8 +30,12 @@ def _area_after(cfg, steps):
     return float((rho[0] / np.maximum(rho[0] + rho[1], 1e-30) > 0.9).sum())
 
 
-@pytest.mark.parametrize("lam", [128, pytest.param(256, marks=pytest.mark.skipif(
-    os.environ.get("LBM_STUDIES") != "1", reason="long study; set LBM_STUDIES=1 to run it"))])
+_long = pytest.mark.skipif(os.environ.get("LBM_STUDIES") != "1",
+                           reason="long study; set LBM_STUDIES=1 to run it")
+
+
+@pytest.mark.parametrize("lam", [128, pytest.param(256, marks=_long),
+                                 pytest.param(512, marks=_long)])
 def test_channel_critical_pressure_vs_planar_young_laplace(gpu_available, lam):
     """Bisection to 1 %.  A water-wet slug forced below its threshold first
     hops most of a wavelength (0.86 lambda at lambda = 128) to a new rest
@@ -43,8 +47,8 @@ def test_channel_critical_pressure_vs_planar_young_laplace(gpu_available, lam):
     deviation).  The test bounds the ratio to [0.95, 2.0] and prints the
     equivalent angle range."""
     from paper_1601_00918_amd import binding
-    equil = 20000 if lam == 128 else 40000
-    budget = 300000 if lam == 128 else 500000
+    equil = {128: 20000, 256: 40000, 512: 80000}[lam]
+    budget = {128: 300000, 256: 500000, 512: 1000000}[lam]
     cfgs, g_yl = [], []
     for nominal, th in THETA2.items():
         cfg = synth.config_channel(lam=lam, theta=nominal)
