@@ -65,6 +65,8 @@ lbm_status check_trackable(const std::vector<lbm_monitor>& mon)
 {
     for (size_t k = 0; k < mon.size(); ++k) {
         const double amp = std::hypot(mon[k].oil_cos, mon[k].oil_sin);
+        if (mon[k].bad_nodes > 0.0 || !std::isfinite(amp + mon[k].mass[0]))
+            continue;  // a non-physical state: the probes flag it as unstable
         if (!(amp > 0.01 * mon[k].mass[0]))
             return fail(LBM_ERR_UNSUPPORTED,
                         "problem %d: the oil density has no first Fourier mode along x "

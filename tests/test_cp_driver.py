@@ -262,3 +262,19 @@ def test_slugs_without_a_first_fourier_mode_are_rejected():
         with pytest.raises(binding._lib.LbmError) as e:
             binding.lbm_cp_drive(Even(plain, [1e-5]), probs, opts)
         assert e.value.status == 6 and "Fourier" in str(e.value)
+
+
+def test_non_finite_states_are_flagged_not_refused():
+    """A state that is already non-physical when the probes start is reported
+    as unstable (as a probe that turns non-physical is), not refused as an
+    untrackable slug."""
+    probs, plain = _problems([1e-5])
+
+    class Broken(FakeEngine):
+        def monitors(self):
+            out = super().monitors()
+            for m in out:
+                m["oil_cos"], m["oil_sin"], m["bad_nodes"] = float("nan"), float("nan"), 7.0
+            return out
+    r = binding.lbm_cp_drive(Broken(plain, [1e-5]), probs, binding.cp_options())[0]
+    assert r["flags"] & binding._lib.CP_UNSTABLE
