@@ -127,3 +127,33 @@ def test_tube_critical_pressure_in_binary16_storage(gpu_available):
     print({k: (v["g_crit"], v["flags"]) for k, v in out.items()})
     assert all(v["flags"] & ~binding._lib.CP_UNDECIDED == 0 for v in out.values())
     assert abs(out["f16"]["g_crit"] / out["f32"]["g_crit"] - 1) <= 0.02
+
+
+@pytest.mark.skipif(__import__("os").environ.get("LBM_STUDIES") != "1",
+                    reason="long study; set LBM_STUDIES=1 to run it")
+def test_full_size_tube_critical_pressure_binary16(gpu_available):
+    """The full-size tube workload: 512 x 128 x 128, r(x) = 40 + 16 cos(2 pi x /
+    256) (neck radius 24), a slug of 384 nodes, binary16 storage, probes of up
+    to 100,000 steps, theta = 90 deg, bisection to 2 %: the critical forcing
+    against the axisymmetric Young-Laplace value for the measured slug volume
+    (the smaller tubes give 0.85-0.95 of it)."""
+    import numpy as np
+    from paper_1601_00918_amd import binding, binding3d as b3
+    cfg = synth.config_tube(lam=256, r0=40.0, a=16.0, nx=512, ny=128, nz=128, theta=90.0,
+                            slug_len=384, slug_x0=64)
+    sim = b3.Simulation3D(cfg, storage="f16")
+    sim.step(40000)
+    rho = sim.moments()["rho"]
+    vol = float((rho[0] / np.maximum(rho[0] + rho[1], 1e-30) > 0.9).sum())
+    del sim
+    dps, _ = yl.critical_pressure(yl.Channel(40.0, 16.0, 256.0, axisymmetric=True), 90.0, vol)
+    g_yl = dps * SIGMA_3D / (RHO_BAR * cfg["nx"])
+    prob = b3.cp3_problem(cfg, 0.5 * g_yl, 1.5 * g_yl, SIGMA_3D, RHO_BAR, 40000, 100000,
+                          min_steps=20000)
+    r = b3.lbm3d_critical_pressure(
+        [prob], binding.cp_options(storage="f16", rel_tol=0.02, chunk_steps=1000,
+                                   still_chunks=3, verify_bracket=1))[0]
+    print("volume %.0f g_YL %.4e result %s ratio %.3f" % (vol, g_yl, r, r["g_crit"] / g_yl),
+          flush=True)
+    assert r["flags"] & ~binding._lib.CP_UNDECIDED == 0
+    assert abs(r["g_crit"] / g_yl - 1) <= 0.25
