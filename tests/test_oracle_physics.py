@@ -390,3 +390,7 @@ def test_tube_contact_angle_detection_recovers_a_known_cap(theta):
     frac = 0.5 * (1.0 - np.tanh((X - xs) / 1.5)) * mask
     got, _, _ = an.tube_meniscus_contact_angle(frac, mask, xm - 3.0, oil_left=True, window=12)
     assert got == pytest.approx(theta, abs=0.5)
+    # the mirror image: oil on the +x side of a rear meniscus
+    back, _, _ = an.tube_meniscus_contact_angle(frac[:, :, ::-1], mask[:, :, ::-1],
+                                                nx - 1 - (xm - 3.0), oil_left=False, window=12)
+    assert back == pytest.approx(theta, abs=0.5)
