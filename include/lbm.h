@@ -181,6 +181,20 @@ const char* lbm_last_error(void);
 /* Library version string. */
 const char* lbm_version(void);
 
+/*
+ * Streaming copy of `bytes` bytes from device src to device dst (a
+ * measurement aid, not part of the method): 16-byte nontemporal loads and
+ * stores over a grid-stride loop of `blocks` workgroups of 256 lanes, four
+ * vectors per lane in flight.  It moves data the way the step kernels do
+ * (every byte read once and written once) and nothing else, so its rate is
+ * the bandwidth ceiling the step's HBM fraction is read against.  src and dst
+ * 16-byte aligned and not overlapping, bytes a multiple of 4, blocks >= 1;
+ * otherwise LBM_ERR_INVALID (lbm_last_error is not set).  Enqueues on
+ * hip_stream and returns.
+ */
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t blocks,
+                           void* hip_stream);
+
 /* Workspace bytes lbm_init needs for these instances. */
 lbm_status lbm_required_bytes(const lbm_geom* geoms, int32_t n_inst, int32_t storage,
                               size_t* bytes);
@@ -282,7 +296,9 @@ typedef struct {
  */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial, lbm_tune_report* report);
 
-/* Release the context (not the caller's workspace or stream). */
+/* Release the context (not the caller's workspace or stream).  Waits for the
+ * work the context queued on its stream first, so the workspace may be freed
+ * as soon as this returns.  NULL is ignored. */
 void lbm_destroy(lbm_ctx* ctx);
 
 /* ------------------------------------------------------------------------

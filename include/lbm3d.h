@@ -135,7 +135,9 @@ lbm_status lbm3d_get_tiling(const lbm3d_ctx* ctx, int32_t* bx, int32_t* by,
 lbm_status lbm3d_snapshot_save(lbm3d_ctx* ctx);
 lbm_status lbm3d_snapshot_restore(lbm3d_ctx* ctx);
 
-/* Release the context (not the caller's workspace or stream). */
+/* Release the context (not the caller's workspace or stream).  Waits for the
+ * work the context queued on its stream first, so the workspace may be freed
+ * as soon as this returns.  NULL is ignored. */
 void lbm3d_destroy(lbm3d_ctx* ctx);
 
 /* ------------------------------------------------------------------------

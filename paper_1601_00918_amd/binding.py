@@ -271,8 +271,8 @@ def lbm_critical_pressure(problems, opts=None, device="cuda", stream=None):
 
     _lib.load()
     nbytes = lbm_cp_required_bytes(problems)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    st = stream if stream is not None else torch.cuda.Stream(ws.device)
+    st = stream if stream is not None else torch.cuda.Stream(torch.device(device))
+    ws = workspace_on(st, nbytes, device)
     res = (LbmCpResult * len(problems))()
     o = opts if opts is not None else cp_options()
     check(_lib.load().lbm_critical_pressure(_arr(problems, LbmCpProblem), len(problems),
@@ -332,6 +332,19 @@ def lbm_cp_drive(engine, problems, opts=None):
 
 
 # ------------------------------------------------------------- convenience ---
+def workspace_on(stream, nbytes, device):
+    """A torch byte buffer allocated on the stream the library will use it on
+    (torch's current stream if None), so the caching allocator orders its
+    reuse after that stream's work: a block freed by other streams' pending
+    kernels is never handed to it, and once freed it is handed out again only
+    behind the library's queued work."""
+    import torch  # device memory and streams only
+    if stream is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
 class Simulation:
     """A context plus the torch device workspace that backs it.
 
@@ -355,7 +368,7 @@ class Simulation:
             inits.append(i)
         self.fluids = fluids
         nbytes = lbm_required_bytes(geoms, storage, snapshot)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.workspace = workspace_on(stream, nbytes, device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(
             self.workspace.device)
         self.ctx = lbm_init(geoms, fluids, inits, storage, self.workspace.data_ptr(), nbytes,

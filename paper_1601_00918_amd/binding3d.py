@@ -7,6 +7,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
+from .binding import workspace_on
 from ._lib import (GEOM3_BOX, GEOM3_MASK, GEOM3_TUBE, INIT3_DROPLET, INIT3_SLUG, INIT3_UNIFORM,
                    OPT_SNAPSHOT, STORE_BF16, STORE_F16, STORE_F32, Lbm3dCpProblem, Lbm3dFluid,
                    Lbm3dGeom, Lbm3dInitFields, LbmCpOptions, LbmCpResult, LbmMonitor, check)
@@ -200,8 +201,8 @@ def lbm3d_critical_pressure(problems, opts=None, device="cuda", stream=None):
     o = opts if opts is not None else cp_options()
     storage = {STORE_F32: "f32", STORE_F16: "f16", STORE_BF16: "bf16"}[o.storage]
     nbytes = lbm3d_cp_required_bytes(problems, storage)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    st = stream if stream is not None else torch.cuda.Stream(ws.device)
+    st = stream if stream is not None else torch.cuda.Stream(torch.device(device))
+    ws = workspace_on(st, nbytes, device)
     res = (LbmCpResult * len(problems))()
     arr = (Lbm3dCpProblem * len(problems))(*problems)
     check(_lib.load().lbm3d_critical_pressure(arr, len(problems), ctypes.byref(o),
@@ -234,7 +235,7 @@ class Simulation3D:
         self.fluid = fluid
         self.shape = (int(cfg["nz"]), int(cfg["ny"]), int(cfg["nx"]))
         nbytes = lbm3d_required_bytes(geom, storage, snapshot)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.workspace = workspace_on(stream, nbytes, device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(
             self.workspace.device)
         self.ctx = lbm3d_init(geom, fluid, init, storage, self.workspace.data_ptr(), nbytes,

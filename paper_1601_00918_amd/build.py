@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_driver.cpp", "lbm_mlp.hip",
-           "lbm3d_kernels.hip", "lbm3d_runtime.cpp"]
+           "lbm3d_kernels.hip", "lbm3d_runtime.cpp", "lbm_copy.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -607,6 +607,13 @@ lbm_status lbm3d_snapshot_restore(lbm3d_ctx* c)
     return LBM_OK;
 }
 
-void lbm3d_destroy(lbm3d_ctx* c) { delete c; }
+void lbm3d_destroy(lbm3d_ctx* c)
+{
+    // Queued steps (graph replays included) still use the caller's workspace:
+    // drain them before the caller can free it.
+    if (c)
+        (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
 
 }  // extern "C"

@@ -1064,6 +1064,13 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial, lbm_tune_report* re
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+void lbm_destroy(lbm_ctx* c)
+{
+    // Queued steps (graph replays included) still use the caller's workspace:
+    // drain them before the caller can free it.
+    if (c)
+        (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
 
 }  // extern "C"

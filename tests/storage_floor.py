@@ -10,6 +10,11 @@ tolerances are a multiple of it.  Arithmetic stays FP64: only the rounding of
 the stored state is emulated.
 
     python tests/storage_floor.py            # prints the floors after 1000 steps
+    python tests/storage_floor.py --write    # also stores them in
+                                             # tests/golden/storage_floor.json
+
+Format "f32" rounds every population to binary32 instead: the floor of the
+FP32 storage itself (arithmetic still FP64).
 """
 import os
 import sys
@@ -69,7 +74,10 @@ def _sr(v, fmt, rng):
 
 def reencode(f, rho, mask, idx, fmt, rng):
     """f: pulled populations [2, 9, ny, nx] after a step whose sources had
-    densities rho [2, ny, nx] (before the step); returns the decoded state."""
+    densities rho [2, ny, nx] (before the step); returns the decoded state.
+    fmt "f32": every population rounded to binary32 (the FP32 storage)."""
+    if fmt == "f32":
+        return f.astype(np.float32).astype(np.float64)
     ny, nx = mask.shape
     out = np.empty_like(f)
     fluid = (mask == 1)
@@ -107,11 +115,21 @@ def floor(cfg, fmt, steps=1000, seed=5):
 
 
 if __name__ == "__main__":
+    import json
     cfgs = {"droplet": synth.config_droplet(n=128, r=20.0),
             "poiseuille": synth.config_poiseuille(),
             "channel": synth.config_channel(lam=64, theta=120.0, g=1e-5)}
-    for fmt in ("f16", "bf16"):
+    table = {"steps": 1000, "seed": 5, "fields": ["rho", "u", "p", "mass_drift"]}
+    for fmt in ("f32", "f16", "bf16"):
+        table[fmt] = {}
         for name, cfg in cfgs.items():
             e = floor(cfg, fmt)
+            table[fmt][name] = [float("%.3e" % v) for v in e]
             print("%-5s %-10s rho %.1e  u %.1e  p %.1e  mass drift %.1e" % ((fmt, name) + e),
                   flush=True)
+    if "--write" in sys.argv:
+        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "storage_floor.json")
+        with open(out, "w") as fh:
+            json.dump(table, fh, indent=1)
+            fh.write("\n")

@@ -66,3 +66,18 @@ def test_autotune_steps_are_real_steps(gpu_available):
     for k in range(len(cfgs)):
         assert np.array_equal(tuned.populations(k), plain.populations(k)), k
     assert rep["ms_after"] <= rep["ms_before"] * 1.05
+
+
+def test_destroy_waits_for_queued_steps(gpu_available):
+    """A context on its own stream replays captured graphs asynchronously;
+    releasing it drains that stream, so the workspace can be freed at once."""
+    import gc
+
+    import torch
+    from paper_1601_00918_amd import Simulation
+    st = torch.cuda.Stream()
+    sim = Simulation([synth.config_channel(lam=256, theta=90.0, g=1e-5)], stream=st)
+    sim.step(640)
+    del sim
+    gc.collect()
+    assert st.query()

@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from oracle import lbm3d as o3
+from tests.gpu_util import assert_monitors_match, fp32_storage_floor_u, velocity_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -94,14 +95,12 @@ def test_moments_after_1000_steps(gpu_available, which):
     erho = _rel(ref["rho"], got["rho"], mask)
     eu = _rel(ref["u"], got["u"], mask)
     ep = _rel(ref["p"][None], got["p"][None], mask)
-    print(which, "rho", erho, "u", eu, "p", ep, flush=True)
+    floor_u = fp32_storage_floor_u(lambda: _oracle(cfg)[0], 1000, mask)
+    print(which, "rho", erho, "u", eu, "(storage floor %.2e)" % floor_u, "p", ep, flush=True)
     assert max(erho) <= 1e-5
     assert max(ep) <= 1e-5
-    m_ref, m_got = ref["mon"], got["mon"]
-    np.testing.assert_allclose(m_got["mass"], m_ref[:2], rtol=1e-6)
-    np.testing.assert_allclose(m_got["oil_cos"], m_ref[5], rtol=1e-5, atol=1e-6 * m_ref[0])
-    np.testing.assert_allclose(m_got["oil_sin"], m_ref[6], rtol=1e-5, atol=1e-6 * m_ref[0])
-    assert m_got["bad_nodes"] == 0
+    assert max(eu) <= velocity_bound(floor_u)
+    assert_monitors_match(ref["mon"], got["mon"])
 
 
 def test_droplet_pressure_jump(gpu_available):

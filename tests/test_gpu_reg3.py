@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import field_rel_err, oracle_lattice
+from tests.gpu_util import (assert_monitors_match, field_rel_err, fp32_storage_floor_u,
+                            oracle_lattice, velocity_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +43,11 @@ def test_moments_after_1000_steps(gpu_available, which):
     erho = field_rel_err(ref["rho"], got["rho"], mask)
     ep = field_rel_err(ref["p"][None], got["p"][None], mask)
     eu = field_rel_err(ref["u"], got["u"], mask)
-    print(which, "rho", erho, "u", eu, "p", ep, flush=True)
+    floor_u = fp32_storage_floor_u(lambda: oracle_lattice(cfg)[0], 1000, mask)
+    print(which, "rho", erho, "u", eu, "(storage floor %.2e)" % floor_u, "p", ep, flush=True)
     assert max(erho) <= 1e-5 and max(ep) <= 1e-5
+    assert max(eu) <= velocity_bound(floor_u)
+    assert_monitors_match(ref["mon"], got["mon"])
     # the option changes the result (against the second-order oracle)
     L2, _, _ = oracle_lattice(dict(cfg, reg_order=2))
     L2.step(1000)

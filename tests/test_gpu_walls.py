@@ -9,7 +9,8 @@ import pytest
 import synth
 from oracle import analysis as an
 from oracle import lbm as orc
-from tests.gpu_util import field_rel_err
+from tests.gpu_util import (assert_monitors_match, field_rel_err, fp32_storage_floor_u,
+                            velocity_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,9 +49,15 @@ def test_few_steps_and_1000_steps_match_oracle(gpu_available, which):
     ref, got = L.moments(), sim.moments(0)
     erho = field_rel_err(ref["rho"], got["rho"], mask)
     ep = field_rel_err(ref["p"][None], got["p"][None], mask)
-    print(which, "rho", erho, "p", ep, "mass drift gpu %.2e oracle %.2e" % (
-        got["mon"]["mass"][0] / sim_mass0(cfg, mask) - 1, ref["mon"][0] / sim_mass0(cfg, mask) - 1))
+    eu = field_rel_err(ref["u"], got["u"], mask)
+    floor_u = fp32_storage_floor_u(lambda: _oracle(cfg)[0], 1000, mask)
+    print(which, "rho", erho, "u", eu, "(storage floor %.2e)" % floor_u, "p", ep,
+          "mass drift gpu %.2e oracle %.2e" % (
+              got["mon"]["mass"][0] / sim_mass0(cfg, mask) - 1,
+              ref["mon"][0] / sim_mass0(cfg, mask) - 1), flush=True)
     assert max(erho) <= 1e-5 and max(ep) <= 1e-5
+    assert max(eu) <= velocity_bound(floor_u)
+    assert_monitors_match(ref["mon"], got["mon"])
 
 
 def sim_mass0(cfg, mask):

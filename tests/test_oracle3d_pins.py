@@ -126,3 +126,50 @@ def test_laplace_law_for_3d_droplets():
     print("1/R", inv_r, "dp", dp, "slope", slope, "intercept", icpt)
     assert slope > 0 and resid < 0.02
     assert abs(icpt) < 0.1 * min(dp)
+
+
+def test_momentum_budget_with_body_force():
+    """D3Q19: from rest on a periodic box with body acceleration g, the
+    physical momentum (u_mix + (F^o + F^w) / (2 rho)) after t steps is
+    M g (t + 1/2), since every collision adds the node's force and the
+    pairwise interaction forces cancel (Eqs. 8-9)."""
+    cfg = synth.config_box3d(n=16, r=5.0, tau=(0.8, 1.1))
+    mask = synth.mask3_of(cfg)
+    g = (1e-5, -4e-6, 2.5e-6)
+    L = o3.Lattice3(o3.Params3(16, 16, 16, tau=cfg["tau"], G=cfg["G"], g=g, periodic_yz=True),
+                    mask, synth.rho03_of(cfg, mask))
+    for t in (0, 1, 10, 40):
+        L.step(t - L.t)
+        m = L.moments()
+        rho = m["rho"].sum(axis=0)
+        mass = m["rho"].sum()
+        for k in range(3):
+            want = mass * g[k] * (t + 0.5)
+            assert abs((rho * m["u"][k]).sum() / want - 1) < 1e-10, (t, k)
+
+
+def test_flat_interface_equal_bulk_pressures():
+    """D3Q19 flat oil band with unequal inventories at rest: equal bulk
+    pressures under the bulk equation of state T0 sum rho - G T0 rho^o rho^w,
+    unequal ones (beyond 1e-4) under the opposite sign of the interaction
+    term.  The bands are 32 rows wide so that their centres are bulk to
+    rounding (24-row bands leave 2e-8 of interface tail at the centre)."""
+    nx, ny, nz = 2, 2, 64
+    mask = np.ones((nz, ny, nx), dtype=np.uint8)
+    z = np.arange(nz)[:, None, None] * np.ones((1, ny, nx))
+    oil = (z >= 16) & (z < 48)
+    rho0 = np.stack([np.where(oil, 1.0, 0.03), np.where(oil, 0.02, 0.6)])
+    G = synth.G_DEFAULT
+    L = o3.Lattice3(o3.Params3(nx, ny, nz, tau=(1.0, 1.0), G=G, periodic_yz=True), mask, rho0)
+    L.step(20000)
+    m = L.moments()
+    po, pw = m["p"][32, 0, 0], m["p"][0, 0, 0]
+    ro, rw = m["rho"][:, 32, 0, 0], m["rho"][:, 0, 0, 0]
+    assert not np.allclose(ro[::-1], rw, rtol=1e-4)
+    assert abs(po / pw - 1) < 1e-9
+    assert abs(po - (T0 * ro.sum() - G * T0 * ro[0] * ro[1])) < 1e-15
+
+    def flipped(r):
+        return T0 * r.sum() + G * T0 * r[0] * r[1]
+
+    assert abs(flipped(ro) / flipped(rw) - 1) > 1e-4

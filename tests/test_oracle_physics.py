@@ -92,6 +92,35 @@ def test_flat_interface_stays_at_rest():
     assert abs(c3b - 15.5) < 0.05
 
 
+def test_flat_interface_equal_bulk_pressures():
+    """A flat interface carries no Laplace jump, so at rest the two bulk
+    phases sit at the same pressure.  Unequal inventories (oil band 1.0 /
+    0.02, water band 0.6 / 0.03) break the mirror symmetry, so the two bulk
+    states differ and only the right equation of state (Sec. 2, the bulk
+    Shan-Chen form T0 sum rho - G T0 rho^o rho^w with the paper's sign of G)
+    gives equal values; the same densities under the opposite sign of the
+    interaction term differ by more than 1e-4."""
+    nx, ny = 4, 64
+    mask = synth.box_mask(nx, ny)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    oil = (y >= 16) & (y < 48)
+    rho0 = np.stack([np.where(oil, 1.0, 0.03), np.where(oil, 0.02, 0.6)])
+    G = synth.G_DEFAULT
+    L = orc.Lattice(orc.Params(nx, ny, tau=(1.0, 1.0), G=G, periodic_y=True), mask, rho0)
+    L.step(20000)
+    m = L.moments()
+    po, pw = m["p"][32, 0], m["p"][0, 0]
+    ro, rw = m["rho"][:, 32, 0], m["rho"][:, 0, 0]
+    assert not np.allclose(ro[::-1], rw, rtol=1e-4)  # the two bulk states differ
+    assert abs(po / pw - 1) < 1e-9
+    np.testing.assert_allclose(m["p"][32], T0 * ro.sum() - G * T0 * ro[0] * ro[1], rtol=1e-15)
+
+    def flipped(r):
+        return T0 * r.sum() + G * T0 * r[0] * r[1]
+
+    assert abs(flipped(ro) / flipped(rw) - 1) > 1e-4
+
+
 @pytest.mark.slow
 def test_laplace_law():
     """Eq. 11: the pressure jump across a static droplet is linear in 1/R

@@ -214,6 +214,30 @@ def test_mass_and_momentum_conservation():
     assert abs(m[2]) < 1e-12 and abs(m[3]) < 1e-12
 
 
+def test_momentum_budget_with_body_force():
+    """Each collision adds the node's total force to its momentum (the shifted
+    equilibrium of Eq. 9 carries rho^a u_mix + F^a), the interaction forces of
+    Eq. 8 cancel in pairs on a periodic lattice, and the reported velocity is
+    u_mix + (F^o + F^w) / (2 rho).  From rest, the physical momentum after t
+    steps is therefore M g (t + 1/2) exactly: a dropped or doubled half-force
+    term, or a force that enters the collision with the wrong weight, breaks
+    it by at least 1 / (2 t + 1)."""
+    cfg = synth.config_droplet(n=32, r=7.0)
+    mask = synth.mask_of(cfg)
+    g = (1e-5, -4e-6)
+    L = orc.Lattice(orc.Params(32, 32, tau=(0.8, 1.1), G=cfg["G"], g=g, periodic_y=True),
+                    mask, synth.rho0_of(cfg, mask))
+    for t in (0, 1, 10, 100):
+        L.step(t - L.t)
+        m = L.moments()
+        rho = m["rho"].sum(axis=0)
+        mass = m["rho"].sum()
+        for k in range(2):
+            want = mass * g[k] * (t + 0.5)
+            assert abs((rho * m["u"][k]).sum() / want - 1) < 1e-10, (t, k)
+            assert abs(m["mon"][2 + k] / want - 1) < 1e-10, (t, k)
+
+
 def test_uniform_flow_is_steady():
     """A uniform state moving at constant velocity is a fixed point of the
     step on a periodic lattice (equilibrium is reproduced by the collision and
