@@ -204,11 +204,11 @@ def measured_traffic(storage, record="step_kernel_batch256_traffic.txt",
 
 def copy_calibration(steps, warmup, nbytes=2 << 30):
     """The bandwidth ceiling: the library's streaming copy kernel
-    (lbm_stream_copy: 16-byte nontemporal loads and stores, every byte read
-    once and written once, like a step) over nbytes at several grid sizes,
-    and torch's own copy kernel beside it.  Each moves exactly 2 * nbytes per
-    launch, which also calibrates the profiler's FETCH_SIZE / WRITE_SIZE
-    counters."""
+    (lbm_stream_copy: one contiguous chunk per workgroup, 16-byte nontemporal
+    loads and stores, every byte read once and written once, like a step)
+    over nbytes at several chunk sizes, and torch's own copy kernel beside it.
+    Each moves exactly 2 * nbytes per launch, which also calibrates the
+    profiler's FETCH_SIZE / WRITE_SIZE counters."""
     import ctypes
 
     import torch
@@ -232,15 +232,15 @@ def copy_calibration(steps, warmup, nbytes=2 << 30):
         return e0.elapsed_time(e1) / steps
 
     rows = []
-    for blocks in (1024, 2048, 4096, 8192, 16384):
+    for chunk in (64 << 10, 256 << 10, 1 << 20):
         def own():
             st = lib.lbm_stream_copy(ctypes.c_void_p(src.data_ptr()),
-                                     ctypes.c_void_p(dst.data_ptr()), nbytes, blocks,
+                                     ctypes.c_void_p(dst.data_ptr()), nbytes, chunk,
                                      ctypes.c_void_p(stream.cuda_stream))
             if st != 0:
                 raise RuntimeError("lbm_stream_copy failed: %d" % st)
         ms = timed(own)
-        rows.append({"kernel": "lbm_stream_copy", "blocks": blocks, "ms": round(ms, 5),
+        rows.append({"kernel": "lbm_stream_copy", "chunk_bytes": chunk, "ms": round(ms, 5),
                      "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)})
     ms = timed(lambda: dst.copy_(src))
     rows.append({"kernel": "torch copy_", "ms": round(ms, 5),

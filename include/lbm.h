@@ -183,16 +183,17 @@ const char* lbm_version(void);
 
 /*
  * Streaming copy of `bytes` bytes from device src to device dst (a
- * measurement aid, not part of the method): 16-byte nontemporal loads and
- * stores over a grid-stride loop of `blocks` workgroups of 256 lanes, four
- * vectors per lane in flight.  It moves data the way the step kernels do
- * (every byte read once and written once) and nothing else, so its rate is
- * the bandwidth ceiling the step's HBM fraction is read against.  src and dst
- * 16-byte aligned and not overlapping, bytes a multiple of 4, blocks >= 1;
+ * measurement aid, not part of the method): each workgroup of 256 lanes
+ * copies one contiguous chunk of chunk_bytes with 16-byte nontemporal loads
+ * and stores, four vectors per lane in flight.  It moves data the way the
+ * step kernels do (every byte read once and written once) and nothing else,
+ * so its rate is the bandwidth ceiling the step's HBM fraction is read
+ * against.  src and dst 16-byte aligned and not overlapping, bytes a multiple
+ * of 4, chunk_bytes a positive multiple of 16384 (256 KiB measured best);
  * otherwise LBM_ERR_INVALID (lbm_last_error is not set).  Enqueues on
  * hip_stream and returns.
  */
-lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, int32_t blocks,
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, size_t chunk_bytes,
                            void* hip_stream);
 
 /* Workspace bytes lbm_init needs for these instances. */

@@ -226,7 +226,7 @@ def load():
                                             ctypes.POINTER(LbmCpOptions), vp, sz, vp,
                                             ctypes.POINTER(LbmCpResult)]
     lib.lbm3d_destroy.argtypes = [vp]
-    lib.lbm_stream_copy.argtypes = [vp, vp, sz, i32, vp]
+    lib.lbm_stream_copy.argtypes = [vp, vp, sz, sz, vp]
     lib.lbm3d_destroy.restype = None
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy",

@@ -31,15 +31,24 @@ def fp32_storage_floor_u(make_lattice, steps, mask):
     """Velocity error (max over components of max|du| / max|u|) that binary32
     storage of the populations alone leaves after `steps`: the FP64 oracle
     against the same oracle run whose populations are rounded to binary32
-    initially and after every step (arithmetic stays FP64).  make_lattice()
-    returns a fresh oracle lattice (D2Q9 or D3Q19) at t = 0."""
-    ref, emu = make_lattice(), make_lattice()
+    after every step (arithmetic stays FP64).  The floor is itself a chaotic
+    sum of roundings (rounding the initial state too moves it by up to 4x on
+    the two-layer Poiseuille), so it is taken as the larger of the runs with
+    and without a rounded initial state.  make_lattice() returns a fresh
+    oracle lattice (D2Q9 or D3Q19) at t = 0."""
+    ref = make_lattice()
     ref.step(steps)
-    emu.f[...] = emu.f.astype(np.float32).astype(np.float64)
-    for _ in range(steps):
-        emu.step(1)
-        emu.f[...] = emu.f.astype(np.float32).astype(np.float64)
-    return max(field_rel_err(ref.moments()["u"], emu.moments()["u"], mask))
+    u_ref = ref.moments()["u"]
+    worst = 0.0
+    for round_initial in (False, True):
+        emu = make_lattice()
+        if round_initial:
+            emu.f[...] = emu.f.astype(np.float32).astype(np.float64)
+        for _ in range(steps):
+            emu.step(1)
+            emu.f[...] = emu.f.astype(np.float32).astype(np.float64)
+        worst = max(worst, max(field_rel_err(u_ref, emu.moments()["u"], mask)))
+    return worst
 
 
 def velocity_bound(floor):
@@ -49,16 +58,22 @@ def velocity_bound(floor):
     return max(1e-5, 4.0 * floor)
 
 
-def assert_monitors_match(ref_mon, got_mon, rtol=1e-5):
+def assert_monitors_match(ref_mon, got_mon, flow_rtol=1e-5, G=0.0):
     """GPU monitors (dict) against the oracle's mon[8] (mass o/w, momentum
-    x/y, oil flux, oil cos/sin moments, bad nodes).  Sums of signed terms are
-    compared on the scale of the total mass times the largest |term| / rho."""
-    mass = ref_mon[0] + ref_mon[1]
+    x/y, oil flux, oil cos/sin moments, bad nodes).  Masses to 1e-6 and the
+    oil distribution moments to 1e-5; the flow sums (momentum, oil flux) to
+    flow_rtol, the velocity tolerance of the same run, on the scale of the
+    largest of them, plus the FP32 rounding of the node forces they contain
+    (2^-24 |G| per unit of mass: at wall nodes the force G rho rho_s / 6 is
+    large and cancels against j node by node, so a flow at rest still sums to
+    a few units in the last place of those forces)."""
     np.testing.assert_allclose(got_mon["mass"], ref_mon[:2], rtol=1e-6)
-    mom_scale = max(abs(ref_mon[2]), abs(ref_mon[3]), abs(ref_mon[4]), 1e-300)
+    mass = ref_mon[0] + ref_mon[1]
+    flow_scale = max(abs(ref_mon[2]), abs(ref_mon[3]), abs(ref_mon[4]), 1e-300)
+    force_floor = 2.0 ** -24 * max(abs(G), 1.0) * mass
     for got, want in ((got_mon["momentum"][0], ref_mon[2]), (got_mon["momentum"][1], ref_mon[3]),
                       (got_mon["oil_flux"], ref_mon[4])):
-        assert abs(got - want) <= rtol * mom_scale + 1e-12 * mass, (got, want)
+        assert abs(got - want) <= flow_rtol * flow_scale + force_floor, (got, want)
     for got, want in ((got_mon["oil_cos"], ref_mon[5]), (got_mon["oil_sin"], ref_mon[6])):
-        assert abs(got - want) <= rtol * abs(want) + 1e-6 * ref_mon[0], (got, want)
+        assert abs(got - want) <= 1e-5 * abs(want) + 1e-6 * ref_mon[0], (got, want)
     assert got_mon["bad_nodes"] == 0 and ref_mon[7] == 0

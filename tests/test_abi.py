@@ -231,3 +231,17 @@ def test_multiple_slugs_validate_on_the_host():
     with pytest.raises(_lib.LbmError) as e:
         b3.lbm3d_init(g3, f3, i3, "f32", 1 << 20, 1 << 30, 0)
     assert e.value.status == 1 and "n_slugs" in str(e.value)
+
+
+def test_stream_copy_validates_on_the_host():
+    """Null or misaligned pointers, sizes not a multiple of 4 and chunk sizes
+    that are not multiples of 16 KiB are rejected before anything is
+    launched."""
+    import ctypes
+    lib = _lib.load()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)  # never dereferenced
+    assert lib.lbm_stream_copy(None, b, 64, 1 << 18, None) == 1
+    assert lib.lbm_stream_copy(a, b, 62, 1 << 18, None) == 1
+    assert lib.lbm_stream_copy(ctypes.c_void_p((1 << 20) + 4), b, 64, 1 << 18, None) == 1
+    assert lib.lbm_stream_copy(a, b, 64, 1000, None) == 1
+    assert lib.lbm_stream_copy(a, b, 64, 0, None) == 1

@@ -100,7 +100,7 @@ def test_moments_after_1000_steps(gpu_available, which):
     assert max(erho) <= 1e-5
     assert max(ep) <= 1e-5
     assert max(eu) <= velocity_bound(floor_u)
-    assert_monitors_match(ref["mon"], got["mon"])
+    assert_monitors_match(ref["mon"], got["mon"], velocity_bound(floor_u), cfg["G"])
 
 
 def test_droplet_pressure_jump(gpu_available):

@@ -47,7 +47,7 @@ def test_moments_after_1000_steps(gpu_available, which):
     print(which, "rho", erho, "u", eu, "(storage floor %.2e)" % floor_u, "p", ep, flush=True)
     assert max(erho) <= 1e-5 and max(ep) <= 1e-5
     assert max(eu) <= velocity_bound(floor_u)
-    assert_monitors_match(ref["mon"], got["mon"])
+    assert_monitors_match(ref["mon"], got["mon"], velocity_bound(floor_u), cfg["G"])
     # the option changes the result (against the second-order oracle)
     L2, _, _ = oracle_lattice(dict(cfg, reg_order=2))
     L2.step(1000)
