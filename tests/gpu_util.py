@@ -27,19 +27,19 @@ def field_rel_err(ref, got, mask):
     return out
 
 
-def fp32_storage_floor_u(make_lattice, steps, mask):
-    """Velocity error (max over components of max|du| / max|u|) that binary32
-    storage of the populations alone leaves after `steps`: the FP64 oracle
-    against the same oracle run whose populations are rounded to binary32
-    after every step (arithmetic stays FP64).  The floor is itself a chaotic
-    sum of roundings (rounding the initial state too moves it by up to 4x on
-    the two-layer Poiseuille), so it is taken as the larger of the runs with
-    and without a rounded initial state.  make_lattice() returns a fresh
-    oracle lattice (D2Q9 or D3Q19) at t = 0."""
+def fp32_storage_floor(make_lattice, steps, mask):
+    """Field errors (max over components of max|d| / max|ref|, for rho, u
+    and p) that binary32 storage of the populations alone leaves after
+    `steps`: the FP64 oracle against the same oracle run whose populations
+    are rounded to binary32 after every step (arithmetic stays FP64).  The
+    floor is itself a chaotic sum of roundings (rounding the initial state
+    too moves it by up to 4x on the two-layer Poiseuille), so each field
+    takes the larger of the runs with and without a rounded initial state.
+    make_lattice() returns a fresh oracle lattice (D2Q9 or D3Q19) at t = 0."""
     ref = make_lattice()
     ref.step(steps)
-    u_ref = ref.moments()["u"]
-    worst = 0.0
+    R = ref.moments()
+    worst = {"rho": 0.0, "u": 0.0, "p": 0.0}
     for round_initial in (False, True):
         emu = make_lattice()
         if round_initial:
@@ -47,14 +47,23 @@ def fp32_storage_floor_u(make_lattice, steps, mask):
         for _ in range(steps):
             emu.step(1)
             emu.f[...] = emu.f.astype(np.float32).astype(np.float64)
-        worst = max(worst, max(field_rel_err(u_ref, emu.moments()["u"], mask)))
+        M = emu.moments()
+        for k in worst:
+            a, b = (R[k], M[k]) if k != "p" else (R[k][None], M[k][None])
+            worst[k] = max(worst[k], max(field_rel_err(a, b, mask)))
     return worst
 
 
+def fp32_storage_floor_u(make_lattice, steps, mask):
+    """The velocity part of fp32_storage_floor."""
+    return fp32_storage_floor(make_lattice, steps, mask)["u"]
+
+
 def velocity_bound(floor):
-    """Velocity tolerance of a 1000-step FP32 parity test: the 1e-5 moment
-    bar, or four times the binary32 storage floor where that floor alone is
-    larger (the GPU adds FP32 arithmetic rounding to the storage rounding)."""
+    """Tolerance of a field after a long FP32 parity run: the 1e-5 moment bar,
+    or four times the binary32 storage floor of that field where the floor
+    alone is larger (the GPU adds FP32 arithmetic rounding to the storage
+    rounding; measured 1.5-2.5 x the floor)."""
     return max(1e-5, 4.0 * floor)
 
 

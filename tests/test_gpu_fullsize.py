@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import field_rel_err, oracle_lattice
+from tests.gpu_util import field_rel_err, fp32_storage_floor_u, oracle_lattice, velocity_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +24,8 @@ def test_full_batch_conserves_mass_and_matches_sampled_instances(gpu_available):
     # bounce-back and the pull step conserve each species' mass exactly; only
     # FP32 rounding of the stored populations remains
     assert bad == 0 and drift <= 1e-6
-    # sampled instances: the first of each of the two smallest wavelengths
-    sampled = [next(k for k, c in enumerate(cfgs) if c["lam"] == lam) for lam in (64, 128)]
+    # sampled instances: the first of each wavelength, element by element
+    sampled = [next(k for k, c in enumerate(cfgs) if c["lam"] == lam) for lam in (64, 128, 256, 512)]
     for k in sampled:
         L, mask, _ = oracle_lattice(cfgs[k])
         L.step(100)
@@ -33,9 +33,12 @@ def test_full_batch_conserves_mass_and_matches_sampled_instances(gpu_available):
         got = sim.moments(k)
         erho = max(field_rel_err(ref["rho"], got["rho"], mask))
         ep = max(field_rel_err(ref["p"][None], got["p"][None], mask))
-        print("instance %d (lambda %d): rho %.2e p %.2e" % (k, cfgs[k]["lam"], erho, ep),
-              flush=True)
+        eu = max(field_rel_err(ref["u"], got["u"], mask))
+        floor_u = fp32_storage_floor_u(lambda: oracle_lattice(cfgs[k])[0], 100, mask)
+        print("instance %d (lambda %d): rho %.2e u %.2e (floor %.2e) p %.2e" % (
+            k, cfgs[k]["lam"], erho, eu, floor_u, ep), flush=True)
         assert erho <= 1e-5 and ep <= 1e-5
+        assert eu <= velocity_bound(floor_u)
 
 
 @pytest.mark.parametrize("storage,G", [("f32", synth.G_DEFAULT), ("f16", 0.0)])
