@@ -57,6 +57,25 @@ lbm_status lbm_mlp_backward(const float* params, const float* X, const float* y,
                             const float* t, int32_t B, float* grad, float* loss, void* ws,
                             size_t ws_bytes, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): lbm_mlp_forward followed by lbm_mlp_backward on the same batch,
+ * with the activations and deltas kept in a fixed device array of the
+ * library instead of a caller workspace.  Writes y[B], grad[LBM_MLP_PARAMS]
+ * and (if not NULL) loss[0], bit for bit as the two calls would with a
+ * workspace.  1 <= B <= LBM_MLP_NOALLOC_MAX_BATCH, else LBM_ERR_INVALID.
+ * The array holds 9 x 2048 x 128 + 128 floats (9.4 MB); each device the
+ * library runs on keeps its own copy until the process ends, and every call
+ * on a device shares it: calls that overlap on one device (two streams, two
+ * threads) race and their results are undefined.  Allocates nothing; the
+ * first call on a device looks up that device's copy (no allocation either).
+ */
+#define LBM_MLP_NOALLOC_MAX_BATCH 2048
+lbm_status lbm_mlp_gradient_noalloc(const float* params, const float* X, const float* t,
+                                    int32_t B, float* y, float* grad, float* loss,
+                                    void* hip_stream);
+
 /* One Adam step k >= 1 on params, in place, with first / second moment
  * vectors m, v (LBM_MLP_PARAMS each, zero before step 1). */
 lbm_status lbm_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t k,

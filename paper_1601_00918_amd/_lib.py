@@ -31,7 +31,7 @@ EXPORTED = [
     "lbm3d_moments", "lbm3d_monitors", "lbm3d_get_populations", "lbm3d_fluid_mask",
     "lbm3d_set_tiling", "lbm3d_get_tiling", "lbm3d_snapshot_save", "lbm3d_snapshot_restore",
     "lbm3d_destroy", "lbm3d_cp_required_bytes", "lbm3d_critical_pressure",
-    "lbm_stream_copy",
+    "lbm_stream_copy", "lbm_mlp_gradient_noalloc",
 ]
 
 GEOM3_BOX, GEOM3_TUBE, GEOM3_MASK = 0, 1, 2
@@ -227,6 +227,7 @@ def load():
                                             ctypes.POINTER(LbmCpResult)]
     lib.lbm3d_destroy.argtypes = [vp]
     lib.lbm_stream_copy.argtypes = [vp, vp, sz, sz, vp]
+    lib.lbm_mlp_gradient_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.lbm3d_destroy.restype = None
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_version", "lbm_time", "lbm_destroy",

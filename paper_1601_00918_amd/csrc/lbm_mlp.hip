@@ -20,6 +20,17 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+
+// Fixed scratch of lbm_mlp_gradient_noalloc: the workspace of the largest
+// batch it accepts (LBM_MLP_NOALLOC_MAX_BATCH is a multiple of 16 samples, so
+// rows_padded(B) stays within it for every accepted B).  Each device that
+// loads the library holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel: the address of the current
+// device's copy comes from noalloc_scratch().
+constexpr size_t kScratchFloats =
+    9 * (size_t)LBM_MLP_NOALLOC_MAX_BATCH * LBM_MLP_HIDDEN + LBM_MLP_NOALLOC_MAX_BATCH / 16;
+static __device__ __align__(256) float scratch[kScratchFloats];
 
 namespace {
 
@@ -287,6 +298,59 @@ __global__ void mlp_adam_kernel(float* __restrict__ P, const float* __restrict__
 
 size_t ws_bytes_for(int B) { return sizeof(float) * (9 * rows_padded(B) * kH + rows_padded(B) / kRows); }
 
+static_assert(LBM_MLP_NOALLOC_MAX_BATCH % kRows == 0, "scratch batch must be a multiple of 16");
+static_assert(kScratchFloats == 9 * (size_t)LBM_MLP_NOALLOC_MAX_BATCH * kH +
+                                    LBM_MLP_NOALLOC_MAX_BATCH / kRows,
+              "scratch holds the workspace of the largest accepted batch");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device
+// (with that device current) and kept.
+lbm_status noalloc_scratch(float** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return lbm::fail(LBM_ERR_DEVICE, "lbm_mlp_gradient_noalloc: hipGetDevice: %s",
+                         hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return lbm::fail(LBM_ERR_UNSUPPORTED, "lbm_mlp_gradient_noalloc: device %d beyond %d",
+                         dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return lbm::fail(LBM_ERR_DEVICE,
+                             "lbm_mlp_gradient_noalloc: hipGetSymbolAddress(scratch): %s",
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+// The four launches of one forward and backward pass over workspace ws.
+hipError_t launch_forward_backward(const float* params, const float* X, const float* t, int B,
+                                   float* y, float* grad, float* loss, float* ws,
+                                   hipStream_t st)
+{
+    const size_t Bp = rows_padded(B);
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)(Bp / kRows)), dim3(kThreads), 0, st,
+                       params, X, B, Bp, y, ws);
+    hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)(Bp / kRows)), dim3(kThreads), 0, st,
+                       params, y, t, B, Bp, ws);
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(32), dim3(kThreads), 0, st, Bp,
+                       (const float*)ws, grad);
+    const int small = kH * kIn + 4 * kH + 1;
+    hipLaunchKernelGGL(mlp_grad_small_kernel, dim3((small + 255) / 256), dim3(256), 0, st, X, y,
+                       t, B, Bp, (const float*)ws, grad, loss);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 using lbm::fail;
@@ -336,6 +400,27 @@ lbm_status lbm_mlp_backward(const float* params, const float* X, const float* y,
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(LBM_ERR_DEVICE, "lbm_mlp_backward: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_mlp_gradient_noalloc(const float* params, const float* X, const float* t,
+                                    int32_t B, float* y, float* grad, float* loss,
+                                    void* hip_stream)
+{
+    if (!params || !X || !t || !y || !grad || B < 1)
+        return fail(LBM_ERR_INVALID, "lbm_mlp_gradient_noalloc: null pointer or B < 1");
+    if (B > LBM_MLP_NOALLOC_MAX_BATCH)
+        return fail(LBM_ERR_INVALID,
+                    "lbm_mlp_gradient_noalloc: B = %d exceeds the fixed scratch of %d samples",
+                    (int)B, LBM_MLP_NOALLOC_MAX_BATCH);
+    float* ws = nullptr;
+    const lbm_status st = noalloc_scratch(&ws);
+    if (st != LBM_OK)
+        return st;
+    const hipError_t e = launch_forward_backward(params, X, t, (int)B, y, grad, loss, ws,
+                                                 (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "lbm_mlp_gradient_noalloc: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 

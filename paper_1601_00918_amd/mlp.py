@@ -44,6 +44,22 @@ def backward(params, X, y, t, grad, ws, loss=None, stream=None):
           "lbm_mlp_backward")
 
 
+NOALLOC_MAX_BATCH = 2048
+
+
+def gradient_noalloc(params, X, t, y, grad, loss=None, stream=None):
+    """forward() then backward() on one batch (B <= NOALLOC_MAX_BATCH) with
+    the library's fixed device scratch instead of a workspace: nothing is
+    allocated.  Calls that overlap on one device race."""
+    B = X.shape[0]
+    assert params.numel() == N_PARAMS and X.shape[1] == N_IN and y.numel() >= B
+    check(_lib.load().lbm_mlp_gradient_noalloc(_ptr(params), _ptr(X), _ptr(t), B, _ptr(y),
+                                               _ptr(grad),
+                                               _ptr(loss) if loss is not None else ctypes.c_void_p(0),
+                                               _stream(stream)),
+          "lbm_mlp_gradient_noalloc")
+
+
 def adam(params, grad, m, v, k, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     check(_lib.load().lbm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(k),
                                    float(lr), float(beta1), float(beta2), float(eps),

@@ -106,6 +106,13 @@ def test_mlp_entry_points_validate_on_the_host():
     null = ctypes.c_void_p(0)
     assert lib.lbm_mlp_forward(null, null, 4, null, null, 0, null) == 1
     assert lib.lbm_mlp_adam(null, null, null, null, 0, 1e-3, 0.9, 0.999, 1e-8, null) == 1
+    # the allocation-free variant: null pointers, B < 1 and B beyond its fixed
+    # scratch are rejected before any device call (never dereferenced)
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.lbm_mlp_gradient_noalloc(null, fake, fake, 4, fake, fake, null, null) == 1
+    assert lib.lbm_mlp_gradient_noalloc(fake, fake, fake, 0, fake, fake, null, null) == 1
+    assert lib.lbm_mlp_gradient_noalloc(fake, fake, fake, 2049, fake, fake, null, null) == 1
+    assert b"2048" in lib.lbm_last_error()
 
 
 def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
