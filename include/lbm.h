@@ -58,10 +58,13 @@ typedef enum {
     LBM_GEOM_BOX = 0,     /* every node fluid, periodic in x and y */
     LBM_GEOM_CHANNEL = 1, /* walls at y = y_c +- (h0 + a cos(2 pi x / lambda)),
                              y_c = (ny - 1) / 2 + y_offset; node fluid iff |y - y_c| < h(x)
-                             (a = 0: flat plates).  Rows outside 0..ny-1 are solid. */
+                             (a = 0: flat plates), except inside the optional island
+                             (island_h, island_len below).  Rows outside 0..ny-1 are
+                             solid. */
     LBM_GEOM_MASK = 2     /* host mask [ny][nx], 1 = fluid; the fluid nodes of every
-                             column must form one contiguous run of rows, and rows
-                             outside 0..ny-1 are solid */
+                             column must form at most two contiguous runs of rows
+                             (two runs: a bypass, two flow paths side by side), and
+                             rows outside 0..ny-1 are solid */
 } lbm_geom_kind;
 
 typedef struct {
@@ -85,6 +88,15 @@ typedef struct {
     double y_offset;       /* LBM_GEOM_CHANNEL: centre line at y_c = (ny - 1) / 2 +
                               y_offset (|y_offset| <= 1), to place walls off the
                               lattice */
+    double island_h;       /* LBM_GEOM_CHANNEL bypass (the paper's closing section
+                              names bypass channels as further work): a solid island
+                              |y - y_c| < island_h over the columns whose distance
+                              to the nearest multiple of lambda is below
+                              island_len / 2 (the wide part of every period), which
+                              splits the channel there into two parallel branches.
+                              0 (or island_len 0): no island.  Not with wall_interp
+                              (LBM_ERR_UNSUPPORTED). */
+    double island_len;
 } lbm_geom;
 
 /* Fluid parameters of one instance. */

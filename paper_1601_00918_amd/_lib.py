@@ -53,7 +53,8 @@ class LbmGeom(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("wall_interp", ctypes.c_int32), ("lam", ctypes.c_double),
                 ("h0", ctypes.c_double), ("a", ctypes.c_double),
-                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("y_offset", ctypes.c_double)]
+                ("mask", ctypes.POINTER(ctypes.c_uint8)), ("y_offset", ctypes.c_double),
+                ("island_h", ctypes.c_double), ("island_len", ctypes.c_double)]
 
 
 class LbmFluid(ctypes.Structure):

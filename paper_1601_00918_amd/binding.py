@@ -27,12 +27,13 @@ def lbm_version():
 
 # ------------------------------------------------------------- structs -------
 def geom_struct(kind, nx, ny, lam=0.0, h0=0.0, a=0.0, mask=None, _keep=None, wall_interp=0,
-                y_offset=0.0):
+                y_offset=0.0, island=(0.0, 0.0)):
     g = LbmGeom()
     g.kind = _GEOM_KINDS[kind] if isinstance(kind, str) else int(kind)
     g.nx, g.ny = int(nx), int(ny)
     g.lam, g.h0, g.a = float(lam), float(h0), float(a)
     g.wall_interp, g.y_offset = int(wall_interp), float(y_offset)
+    g.island_h, g.island_len = float(island[0]), float(island[1])
     if mask is not None:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         assert m.shape == (ny, nx)
@@ -81,7 +82,8 @@ def structs_from_config(cfg, rho0=None, keep=None):
     explicit initial field."""
     geom = geom_struct(cfg["kind"], cfg["nx"], cfg["ny"], cfg.get("lam", 0.0),
                        cfg.get("h0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep,
-                       cfg.get("wall_interp", 0), cfg.get("y_offset", 0.0))
+                       cfg.get("wall_interp", 0), cfg.get("y_offset", 0.0),
+                       cfg.get("island", (0.0, 0.0)))
     fluid = fluid_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)), cfg.get("g", (0, 0)),
                          cfg.get("reg_order", 2))
     if rho0 is not None:

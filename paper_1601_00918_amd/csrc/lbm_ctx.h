@@ -20,7 +20,7 @@ struct InstHost {
     int pitch;
     int64_t elems;  // elements of this instance in one buffer (rstride * ny)
     int64_t f_off;
-    std::vector<Col> cols;  // per column fluid run
+    std::vector<Col> cols;  // per column fluid runs
 };
 
 // Workspace carving (byte offsets into the caller's device workspace).

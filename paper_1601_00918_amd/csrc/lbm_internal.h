@@ -28,6 +28,7 @@ struct InstDev {
     float rho_s[2];     // wall potentials
     float g[2];         // body acceleration
     int32_t reg3;       // 1: third-order Hermite regularization
+    int32_t gaps;       // 1: some column holds two fluid runs (a bypass)
     double Gd;          // G in double (pressure export)
     // Interpolated walls (channel, FP32 storage): the wall fraction q of every
     // wall link, [nx][kWallSlots][8] (see wall_slot), or null for half-way
@@ -54,10 +55,24 @@ struct Item {
     int32_t inst, x0, y0, y1;
 };
 
-// Column table entry: the fluid rows of a column are lo..hi (empty if lo > hi).
+// Column table entry: the fluid rows of a column are lo..hi (empty if lo > hi)
+// except the solid gap glo..ghi between two runs (no gap if glo > ghi).
 struct Col {
-    int32_t lo, hi;
+    int32_t lo, hi, glo, ghi;
 };
+
+__host__ __device__ inline bool col_fluid(const Col& c, int y)
+{
+    return (y >= c.lo) & (y <= c.hi) & ((y < c.glo) | (y > c.ghi));
+}
+
+// Fluid nodes of a column.
+__host__ __device__ inline int col_nodes(const Col& c)
+{
+    const int run = c.hi >= c.lo ? c.hi - c.lo + 1 : 0;
+    const int gap = c.ghi >= c.glo ? c.ghi - c.glo + 1 : 0;
+    return run - gap;
+}
 
 // Initial-state description for the init kernel (one instance per launch).
 struct InitDev {
@@ -81,7 +96,8 @@ constexpr int kMonWidth = 8;
 
 // Launchers (lbm_kernels.hip).  All enqueue on `stream` and return the launch
 // status.  ext selects the extended step kernels, with the branches of the
-// optional features (taken by instances with reg3 set or a wall table).
+// optional features (taken by instances with reg3 set, a wall table or
+// two-run columns).
 // The rounding sequence of the 16-bit formats is keyed by the step number
 // seed + (seed_dev ? *seed_dev : 0) (seed_dev lets a captured graph take the
 // step number from device memory; see launch_set_seed).

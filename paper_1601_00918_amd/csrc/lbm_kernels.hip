@@ -104,11 +104,6 @@ __device__ __forceinline__ void encode_node(const float (&F)[2][9], const float 
     put32(dst + 9 * plane, rb[0] | (rb[1] << 16));
 }
 
-__device__ __forceinline__ bool in_run(Col c, int y)
-{
-    return y >= c.lo && y <= c.hi;
-}
-
 // Direction constants for a lane-varying direction index.
 __device__ __forceinline__ int dir_cx(int i)
 {
@@ -180,6 +175,18 @@ __device__ __forceinline__ Mom moments9(const float* f)
     m.mxxy = d57 - d86;
     m.mxyy = d57 + d86;
     return m;
+}
+
+// Fluid test of row y in column c: the plain kernels serve instances whose
+// columns hold one run; the extended kernels also test the gap of two-run
+// columns.
+template <bool EXT>
+__device__ __forceinline__ bool col_in(const Col& c, int y)
+{
+    if constexpr (EXT)
+        return col_fluid(c, y);
+    else
+        return (y >= c.lo) & (y <= c.hi);
 }
 
 struct ColG {
@@ -271,7 +278,7 @@ __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy
 // times the row stride in pairs) of row r - 1 + k.  Where x - c_i is solid the
 // half-way bounce-back source f*_opp(i)(x) is used instead (bit i of the
 // returned mask).  Instances are smaller than 4 GiB, so 32-bit offsets suffice.
-template <bool PY, uint32_t PB>
+template <bool PY, uint32_t PB, bool EXT>
 __device__ __forceinline__ uint32_t pull_offsets(const InstDev& P, const int (&rb)[3], int r, int xm,
                                                  int x, int xp, const ColG& g, uint32_t (&off)[9])
 {
@@ -285,7 +292,7 @@ __device__ __forceinline__ uint32_t pull_offsets(const InstDev& P, const int (&r
         if (!PY) {
             const Col cc = cx == 1 ? g.m : (cx == -1 ? g.p : g.c);
             const int sy = r - cy;
-            src_fluid = (sy >= cc.lo) & (sy <= cc.hi);
+            src_fluid = col_in<EXT>(cc, sy);
         }
         const uint32_t o_src = PB * ((uint32_t)(i * P.pitch) + (uint32_t)(srb + sx));
         const uint32_t o_bb = PB * ((uint32_t)(kOpp[i] * P.pitch) + (uint32_t)(rb[1] + x));
@@ -335,7 +342,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
     const int hd = hj < 9 ? hj : 0;
     const int hcx = dir_cx(hd), hcy = dir_cy(hd), hopp = dir_opp(hd);
     const int hsx = hcx == 1 ? hxm : (hcx == -1 ? hxp : hx);
-    Col hgc{0, 0}, hgs{0, 0}, hge{0, 0};  // halo column, its source column, the one beyond
+    Col hgc{0, 0, 1, 0}, hgs{0, 0, 1, 0}, hge{0, 0, 1, 0};  // halo column, its source, the one beyond
     if (!PY && hgrp) {
         hgc = cols[P.col_off + hx];
         hgs = cols[P.col_off + hsx];
@@ -360,7 +367,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
 
     auto row_of = [&](int r) -> int { return PY ? wrapi(r, P.ny) : r; };
     auto node_fluid = [&](const Col& c, int rr) -> bool {
-        return PY ? true : ((rr >= c.lo) & (rr <= c.hi));
+        return PY ? true : col_in<EXT>(c, rr);
     };
     // Reference pair of node (xx, row q); rows outside a channel read as 0.
     auto load_ref = [&](int q, int xx) -> uint32_t {
@@ -394,7 +401,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         fl_next = act && node_fluid(g.c, rr);
         if (fl_next) {
             uint32_t off[9];
-            bb_next = pull_offsets<PY, PB>(P, rb, rr, xm, x, xp, g, off);
+            bb_next = pull_offsets<PY, PB, EXT>(P, rb, rr, xm, x, xp, g, off);
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 rawp[i] = S::load(base + off[i]);
@@ -402,7 +409,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         hfl_next = node_fluid(hgc, rr);
         if (hlane && hfl_next) {
             const int srb = rb[1 - hcy];
-            const bool src_fluid = PY ? true : (((rr - hcy) >= hgs.lo) & ((rr - hcy) <= hgs.hi));
+            const bool src_fluid = PY ? true : col_in<EXT>(hgs, rr - hcy);
             hbb_next = !src_fluid;
             const uint32_t o = src_fluid ? PB * ((uint32_t)(hd * P.pitch) + (uint32_t)(srb + hsx))
                                          : PB * ((uint32_t)(hopp * P.pitch) + (uint32_t)(rb[1] + hx));
@@ -458,7 +465,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                         if (q < 0.5f) {
                             const Col ce = cx == 1 ? g.p : (cx == -1 ? g.m : g.c);
                             const int ye = rr + cy;
-                            use = (ye >= ce.lo) & (ye <= ce.hi);
+                            use = col_fluid(ce, ye);
                             const int xe = cx == 1 ? xp : (cx == -1 ? xm : x);
                             o_extra = PB * ((uint32_t)(kOpp[i] * P.pitch) +
                                             (uint32_t)(ye * RS + xe));
@@ -516,7 +523,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                         bool use = true;
                         if (q < 0.5f) {
                             const int ye = rr + hcy;
-                            use = (ye >= hge.lo) & (ye <= hge.hi);
+                            use = col_fluid(hge, ye);
                             const int xe = hcx == 1 ? hxp : (hcx == -1 ? hxm : hx);
                             o_extra = PB * ((uint32_t)(hopp * P.pitch) +
                                             (uint32_t)(ye * RS + xe));
@@ -789,7 +796,7 @@ __global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ in
             return true;
         if (yy < 0 || yy >= P.ny)
             return false;
-        return in_run(cols[P.col_off + xx], yy);
+        return col_fluid(cols[P.col_off + xx], yy);
     };
     if (!fluid(x, y))
         return;

@@ -50,26 +50,66 @@ constexpr int kGraphSteps = 64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Column entry from a column's fluid predicate over rows 0..ny-1: one run, or
+// two runs with the solid gap between them; false if there are more.
+template <typename F>
+bool column_runs(int ny, F fluid, Col& out)
+{
+    int starts[2], ends[2], n = 0;
+    for (int y = 0; y < ny; ++y) {
+        if (!fluid(y))
+            continue;
+        if (n > 0 && ends[n - 1] == y - 1) {
+            ends[n - 1] = y;
+            continue;
+        }
+        if (n == 2)
+            return false;
+        starts[n] = ends[n] = y;
+        ++n;
+    }
+    if (n == 0)
+        out = Col{0, -1, 1, 0};
+    else if (n == 1)
+        out = Col{starts[0], ends[0], 1, 0};
+    else
+        out = Col{starts[0], ends[1], ends[0] + 1, starts[1] - 1};
+    return true;
+}
+
+// Whether column x of a channel lies under its island (the wide part of
+// every period, where the distance to the nearest multiple of lambda is
+// below island_len / 2).
+bool island_column(const lbm_geom& g, int x)
+{
+    if (!(g.island_h > 0.0) || !(g.island_len > 0.0))
+        return false;
+    const double r = std::fmod((double)x, g.lambda);
+    return std::min(r, g.lambda - r) < 0.5 * g.island_len;
+}
+
 // Fluid runs per column for a geometry; returns false with a message on error.
 bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
 {
-    cols.assign(g.nx, Col{0, -1});
+    cols.assign(g.nx, Col{0, -1, 1, 0});
     if (g.kind == LBM_GEOM_BOX) {
         for (auto& c : cols)
-            c = Col{0, g.ny - 1};
+            c = Col{0, g.ny - 1, 1, 0};
         return true;
     }
     if (g.kind == LBM_GEOM_CHANNEL) {
         const double yc = 0.5 * (g.ny - 1) + g.y_offset;
         for (int x = 0; x < g.nx; ++x) {
             const double h = g.h0 + g.a * std::cos(2.0 * M_PI * (double)x / g.lambda);
-            int lo = g.ny, hi = -1;
-            for (int y = 0; y < g.ny; ++y)
-                if (std::fabs((double)y - yc) < h) {
-                    lo = std::min(lo, y);
-                    hi = std::max(hi, y);
-                }
-            cols[x] = lo <= hi ? Col{lo, hi} : Col{0, -1};
+            const bool isl = island_column(g, x);
+            auto fluid = [&](int y) {
+                const double dy = std::fabs((double)y - yc);
+                return dy < h && !(isl && dy < g.island_h);
+            };
+            if (!column_runs(g.ny, fluid, cols[x])) {
+                err = "channel column " + std::to_string(x) + " has more than two fluid runs";
+                return false;
+            }
         }
         return true;
     }
@@ -79,19 +119,11 @@ bool voxelise(const lbm_geom& g, std::vector<Col>& cols, std::string& err)
             return false;
         }
         for (int x = 0; x < g.nx; ++x) {
-            int lo = -1, hi = -1;
-            for (int y = 0; y < g.ny; ++y)
-                if (g.mask[(size_t)y * g.nx + x]) {
-                    if (lo < 0)
-                        lo = y;
-                    else if (hi != y - 1) {
-                        err = "mask column " + std::to_string(x) +
-                              " has more than one run of fluid rows";
-                        return false;
-                    }
-                    hi = y;
-                }
-            cols[x] = lo >= 0 ? Col{lo, hi} : Col{0, -1};
+            auto fluid = [&](int y) { return g.mask[(size_t)y * g.nx + x] != 0; };
+            if (!column_runs(g.ny, fluid, cols[x])) {
+                err = "mask column " + std::to_string(x) + " has more than two runs of fluid rows";
+                return false;
+            }
         }
         return true;
     }
@@ -123,7 +155,7 @@ bool wall_table(const lbm_geom& g, const std::vector<Col>& cols, std::vector<flo
             for (int j = 1; j < 9; ++j) {
                 const Col& cs = cols[(x - cx[j] + g.nx) % g.nx];
                 const int ys = y - cy[j];
-                if (ys >= cs.lo && ys <= cs.hi)
+                if (col_fluid(cs, ys))
                     continue;
                 const int slot = wall_slot(y, c.lo, c.hi);
                 if (slot < 0) {
@@ -159,6 +191,11 @@ lbm_status check_geom(const lbm_geom& g)
         return fail(LBM_ERR_INVALID, "wall_interp must be 0 or 1");
     if (g.wall_interp && g.kind != LBM_GEOM_CHANNEL)
         return fail(LBM_ERR_UNSUPPORTED, "interpolated walls need the analytic channel geometry");
+    if (!std::isfinite(g.island_h) || !std::isfinite(g.island_len) || g.island_h < 0.0 ||
+        g.island_len < 0.0)
+        return fail(LBM_ERR_INVALID, "island_h and island_len must be finite and >= 0");
+    if (g.wall_interp && g.island_h > 0.0 && g.island_len > 0.0)
+        return fail(LBM_ERR_UNSUPPORTED, "interpolated walls do not support an island");
     if (g.nx < 1 || g.ny < 1 || g.nx > 32768 || g.ny > 32768)
         return fail(LBM_ERR_INVALID, "geometry size %d x %d out of range", g.nx, g.ny);
     // The kernels address an instance with 32-bit byte offsets.
@@ -300,11 +337,12 @@ void fill_inst_params(InstDev& d, const lbm_fluid& f)
 }
 
 // Whether any instance uses an optional feature (third-order regularization,
-// interpolated walls): then the step launches the extended kernels.
+// interpolated walls, two-run columns): then the step launches the extended
+// kernels.
 bool any_ext(const lbm_ctx* c)
 {
     for (const InstDev& d : c->idv)
-        if (d.reg3 || d.wq)
+        if (d.reg3 || d.wq || d.gaps)
             return true;
     return false;
 }
@@ -589,6 +627,10 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         }
         d.col_off = (int32_t)all_cols.size();
         fill_inst_params(d, fluids[k]);
+        d.gaps = 0;
+        for (const Col& cc : h.cols)
+            if (cc.glo <= cc.ghi)
+                d.gaps = 1;
         all_cols.insert(all_cols.end(), h.cols.begin(), h.cols.end());
     }
     // Default tiling.  FP32: the widest block not wider than the widest
@@ -900,7 +942,7 @@ lbm_status lbm_fluid_mask(lbm_ctx* c, int32_t inst, uint8_t* mask)
     const InstHost& h = c->ih[inst];
     for (int y = 0; y < h.ny; ++y)
         for (int x = 0; x < h.nx; ++x)
-            mask[(size_t)y * h.nx + x] = (y >= h.cols[x].lo && y <= h.cols[x].hi) ? 1 : 0;
+            mask[(size_t)y * h.nx + x] = col_fluid(h.cols[x], y) ? 1 : 0;
     return LBM_OK;
 }
 
@@ -975,7 +1017,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial, lbm_tune_report* re
             continue;
         int64_t nodes = 0;
         for (const Col& cc : c->ih[k].cols)
-            nodes += std::max(0, cc.hi - cc.lo + 1);
+            nodes += col_nodes(cc);
         auto it = std::find_if(order.begin(), order.end(),
                                [&](const std::pair<int64_t, int>& b) { return b.second == c->ih[k].nx; });
         if (it == order.end())

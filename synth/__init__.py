@@ -35,14 +35,22 @@ def channel_half_width(x, lam, h0, a):
     return h0 + a * np.cos(2.0 * np.pi * np.asarray(x, dtype=np.float64) / lam)
 
 
-def channel_mask(nx, ny, lam, h0, a, y_offset=0.0):
+def channel_mask(nx, ny, lam, h0, a, y_offset=0.0, island=(0.0, 0.0)):
     """uint8 [ny, nx] fluid mask of a sinusoidal (a > 0) or flat (a = 0) channel
-    whose centre line is y_c = (ny - 1) / 2 + y_offset."""
+    whose centre line is y_c = (ny - 1) / 2 + y_offset.  island = (half-height
+    s, length l): the nodes with |y - y_c| < s in the columns whose distance to
+    the nearest multiple of lam is below l / 2 are solid, which splits the
+    channel there into two branches (a bypass)."""
     x = np.arange(nx, dtype=np.float64)[None, :]
     y = np.arange(ny, dtype=np.float64)[:, None]
     yc = 0.5 * (ny - 1) + y_offset
     h = channel_half_width(x, lam, h0, a)
-    return (np.abs(y - yc) < h).astype(np.uint8)
+    fluid = np.abs(y - yc) < h
+    s, ln = island
+    if s > 0 and ln > 0:
+        r = np.mod(x, lam)
+        fluid &= ~((np.minimum(r, lam - r) < 0.5 * ln) & (np.abs(y - yc) < s))
+    return fluid.astype(np.uint8)
 
 
 def box_mask(nx, ny):
@@ -170,6 +178,21 @@ def config_channel(lam=256, theta=90.0, tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug
                 init=dict(kind="slug", x0=slug_x0, length=slug_len))
 
 
+def config_bypass(lam=64, theta=120.0, tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, island_h=None,
+                  island_len=None, slug_len=None, slug_x0=None):
+    """Sinusoidal channel of the batch family (h0 = lam/8, a = lam/16) whose
+    wide part holds a solid island of half-height lam/32 over lam/2 columns:
+    there the channel splits into two branches, a bypass around the
+    island.  The oil slug (1.5 lam from lam/4 by default) fills both branches
+    where it crosses the islands."""
+    cfg = config_channel(lam=lam, theta=theta, tau=tau, g=g, G=G, slug_len=slug_len,
+                         slug_x0=slug_x0)
+    cfg["island"] = (float(lam // 32 if island_h is None else island_h),
+                     float(lam // 2 if island_len is None else island_len))
+    cfg["name"] = "bypass"
+    return cfg
+
+
 def config_plates(H=32, theta=90.0, tau=(1.0, 1.0), G=G_DEFAULT, nx=None, rho_s=None,
                   offset=0.0):
     """An oil slug at rest between flat plates H nodes apart (a = 0 channel,
@@ -220,7 +243,7 @@ def mask_of(cfg):
     if cfg["kind"] == "box":
         return box_mask(cfg["nx"], cfg["ny"])
     return channel_mask(cfg["nx"], cfg["ny"], cfg["lam"], cfg["h0"], cfg["a"],
-                        cfg.get("y_offset", 0.0))
+                        cfg.get("y_offset", 0.0), cfg.get("island", (0.0, 0.0)))
 
 
 def rho0_of(cfg, mask=None):

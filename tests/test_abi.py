@@ -88,14 +88,30 @@ def test_init_rejects_bad_fluid_and_init_on_host():
     assert e.value.status == 1 and "reg_order" in str(e.value)
 
 
-def test_mask_with_two_fluid_runs_in_a_column_is_unsupported():
+def test_mask_with_three_fluid_runs_in_a_column_is_unsupported():
+    """Two runs per column (a bypass) are supported; a third is rejected on
+    the host."""
     mask = np.ones((10, 8), dtype=np.uint8)
     mask[4, 3] = 0
+    mask[7, 3] = 0
     keep = []
     g = binding.geom_struct("mask", 8, 10, mask=mask, _keep=keep)
     with pytest.raises(_lib.LbmError) as e:
         _try_init([g], [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct("uniform")])
     assert e.value.status == 6 and "column 3" in str(e.value)
+
+
+def test_island_parameters_validate_on_the_host():
+    fl = [binding.fluid_struct((1.0, 1.0), -2.7)]
+    ini = [binding.init_struct("uniform")]
+    g = binding.geom_struct("channel", 256, 26, 64.0, 8.0, 4.0, island=(-1.0, 32.0))
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init([g], fl, ini)
+    assert e.value.status == 1 and "island" in str(e.value)
+    g = binding.geom_struct("channel", 256, 26, 64.0, 8.0, 4.0, wall_interp=1, island=(2.0, 32.0))
+    with pytest.raises(_lib.LbmError) as e:
+        _try_init([g], fl, ini)
+    assert e.value.status == 6 and "island" in str(e.value)
 
 
 def test_mlp_entry_points_validate_on_the_host():
