@@ -150,30 +150,108 @@ def fluid_nodes(cfgs):
     return int(sum(int(synth.mask_of(c).sum()) for c in cfgs))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_configs():
+    """The oracle's timing set: C1 (droplet 128^2), C2 (two-layer Poiseuille
+    256 x 64), C3 (channel lambda = 256, 1024 x 98) and a stratified subset of
+    the 256-channel batch (its first two instances of each wavelength)."""
+    import synth
+    batch = synth.config_batch(n_inst=256, seed=1601)
+    subset = []
+    for lam in (64, 128, 256, 512):
+        subset += [c for c in batch if c["lam"] == lam][:2]
+    return [("C1 droplet 128x128 R=20", [synth.config_droplet(n=128, r=20.0)]),
+            ("C2 two-layer Poiseuille 256x64", [synth.config_poiseuille()]),
+            ("C3 channel lambda=256 1024x98", [synth.config_channel(lam=256, theta=90.0, g=2e-6)]),
+            ("C4 subset: 8 channels of the batch, 2 per lambda", subset)]
+
+
 def cpu_baseline(seconds):
-    """The FP64 oracle on a bounded sample of the batch: the lambda = 128
-    instances' shape (512 x 50), stepped until about `seconds` have passed."""
+    """The FP64 oracle on the host cores, as it stands, on bounded samples:
+    each configuration of cpu_baseline_configs() at one thread and at every
+    thread the oracle uses by default (OMP_NUM_THREADS, else all cores),
+    stepped for about seconds / 8 each.  The reported value is the batch
+    subset at the default thread count, the sample of the benchmark's own
+    workload."""
     import numpy as np  # noqa: F401
     import synth
     from oracle import lbm as orc
 
-    cfg = synth.config_channel(lam=128, theta=60.0, g=1e-6, tau=(0.8, 1.2))
-    mask = synth.mask_of(cfg)
-    L = orc.Lattice(orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"],
-                               rho_s=cfg["rho_s"], g=cfg["g"]), mask, synth.rho0_of(cfg, mask))
-    nf = int(mask.sum())
-    L.step(2)
-    t0 = time.perf_counter()
-    L.step(10)
-    dt = time.perf_counter() - t0
-    n = max(10, int(seconds / max(dt / 10, 1e-6)))
-    t0 = time.perf_counter()
-    L.step(n)
-    dt = time.perf_counter() - t0
-    return {"value": nf * n / dt / 1e6, "unit": "MLUPS", "cores": orc.threads_used(),
-            "kind": "oracle",
-            "sample": "FP64 oracle, one lambda=128 channel of the batch (512x50, %d fluid nodes), "
-                      "%d steps in %.1f s" % (nf, n, dt)}
+    nthreads = orc.threads_used()
+    per = seconds / 8.0
+    runs = []
+    for name, cfgs in cpu_baseline_configs():
+        lats = []
+        nf = 0
+        for c in cfgs:
+            mask = synth.mask_of(c)
+            nf += int(mask.sum())
+            lats.append(orc.Lattice(orc.Params(c["nx"], c["ny"], tau=c["tau"], G=c["G"],
+                                               rho_s=c["rho_s"], g=c["g"],
+                                               periodic_y=(c["kind"] == "box")),
+                                    mask, synth.rho0_of(c, mask)))
+        for threads in (1, nthreads):
+            orc.set_threads(threads)
+            for L in lats:
+                L.step(1)
+            t0 = time.perf_counter()
+            for L in lats:
+                L.step(1)
+            dt1 = time.perf_counter() - t0
+            n = max(1, int(per / max(dt1, 1e-6)))
+            t0 = time.perf_counter()
+            for L in lats:
+                L.step(n)
+            dt = time.perf_counter() - t0
+            runs.append({"config": name, "threads": threads, "fluid_nodes": nf, "steps": n,
+                         "seconds": round(dt, 2), "mlups": round(nf * n / dt / 1e6, 3)})
+            if threads == nthreads == 1:
+                break
+    orc.set_threads(nthreads)
+    main = next(r for r in runs if r["config"].startswith("C4") and r["threads"] == nthreads)
+    return {"value": main["mlups"], "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
+            "sample": "FP64 oracle, %s (%d fluid nodes), %d steps in %.1f s at %d threads; "
+                      "C1-C3 and 1-thread runs in 'runs'" % (
+                          main["config"], main["fluid_nodes"], main["steps"], main["seconds"],
+                          nthreads),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "runs": runs}
+
+
+def gpu_configs_mlups(steps=200, warmup=20):
+    """GPU MLUPS of the oracle's timing set (C1-C3 and the batch subset), FP32,
+    each advanced alone (C1-C3 fit in the device cache, so no HBM fraction is
+    claimed for them)."""
+    import torch
+    import synth
+    from paper_1601_00918_amd import Simulation
+    out = []
+    for name, cfgs in cpu_baseline_configs():
+        nf = sum(int(synth.mask_of(c).sum()) for c in cfgs)
+        sim = Simulation(cfgs)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        sim.step(steps)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out.append({"config": name, "fluid_nodes": nf, "ms_per_step": round(ms, 5),
+                    "mlups": round(nf / ms / 1e3, 1)})
+        del sim
+    return out
 
 
 # Sources of the D2Q9 step kernel; the counter record names their hash.
@@ -255,9 +333,13 @@ def copy_calibration(steps, warmup, nbytes=2 << 30):
 def solves_per_hour(args):
     """Critical-pressure solves per hour: plain single-instance bisection vs
     batched solves with surrogate brackets, on channels of the batch family
-    with lambda ~ U{64, 128} (theta ~ U(30, 150) deg, viscosity ratio
+    (lambda ~ U{--lams}, theta ~ U(30, 150) deg, viscosity ratio
     ~ logU(0.1, 10)).  The surrogate is trained first on batched plain solves
-    of other channels of the same family; its cost is reported apart."""
+    of other channels of the same family; its cost is reported apart.  The
+    gain is split into batching (batched plain vs single plain) and the
+    surrogate (batched surrogate vs batched plain), each per wavelength class
+    as well; single-instance results are checked against the batched ones on
+    a stratified subset (--single-per-lam per wavelength)."""
     import numpy as np
     import torch
     import synth
@@ -266,9 +348,9 @@ def solves_per_hour(args):
 
     SIG, RHO = 0.161, 1.03
     rules = dict(rel_tol=0.005, chunk_steps=500, still_chunks=3)
-    lams = (64, 128)
+    lams = tuple(int(v) for v in args.lams.split(","))
     n_eval = args.solves
-    train = synth.config_cp_set(n_eval, seed=1611, lams=lams)
+    train = synth.config_cp_set(args.train_solves or n_eval, seed=1611, lams=lams)
     evals = synth.config_cp_set(n_eval, seed=1612, lams=lams)
     stream = torch.cuda.Stream()
 
@@ -298,15 +380,16 @@ def solves_per_hour(args):
         return sg.solve(evals, br, SIG, RHO, stream=stream, verify_bracket=2, autotune=1,
                         storage=args.storage, **rules)
     bs, t_bs = timed(batched_sur)
+    log("batched surrogate %.1f s" % t_bs)
     # 3. batched plain (no surrogate), for the split of the gain
     bp, t_bp = timed(lambda: sg.solve(evals, [sg.plain_bracket(c, SIG, RHO) for c in evals],
                                       SIG, RHO, stream=stream, autotune=1,
                                       storage=args.storage, **rules))
     log("batched: surrogate %.1f s, plain %.1f s for %d solves" % (t_bs, t_bp, n_eval))
-    # 4. plain single-instance solves: a stratified subset, two per lambda
+    # 4. plain single-instance solves: a stratified subset per wavelength
     subset = []
     for lam in lams:
-        subset += [i for i, c in enumerate(evals) if c["lam"] == lam][:2]
+        subset += [i for i, c in enumerate(evals) if c["lam"] == lam][:args.single_per_lam]
     per_lam = {lam: [] for lam in lams}
     single = {}
     for i in subset:
@@ -315,28 +398,43 @@ def solves_per_hour(args):
                                        stream=stream, **rules)[0])
         single[i] = r
         per_lam[c["lam"]].append(dt)
-        log("single lambda %d: %.1f s, %d probes" % (c["lam"], dt, r["probes"]))
+        log("single lambda %d: %.1f s, %d probes, g_c %.4e (batched surrogate %.4e)" % (
+            c["lam"], dt, r["probes"], r["g_crit"], bs[i]["g_crit"]))
     mix = {lam: sum(1 for c in evals if c["lam"] == lam) / n_eval for lam in lams}
     t_single = sum(mix[lam] * float(np.mean(per_lam[lam])) for lam in lams)
-    agree = max(abs(bs[i]["g_crit"] / single[i]["g_crit"] - 1) for i in subset)
+    diffs = [abs(bs[i]["g_crit"] / single[i]["g_crit"] - 1) for i in subset]
     plain_rate = 3600.0 / t_single
     rate = 3600.0 * n_eval / t_bs
+    by_lam = {}
+    for lam in lams:
+        idx = [i for i, c in enumerate(evals) if c["lam"] == lam]
+        by_lam[str(lam)] = {
+            "solves": len(idx), "single_s_mean": round(float(np.mean(per_lam[lam])), 2),
+            "probes_batched_surrogate": int(sum(bs[i]["probes"] for i in idx)),
+            "probes_batched_plain": int(sum(bp[i]["probes"] for i in idx)),
+            "steps_batched_surrogate": int(sum(bs[i]["steps"] for i in idx)),
+            "steps_batched_plain": int(sum(bp[i]["steps"] for i in idx))}
     return {
         "metric": "critical-pressure solves/hr, batched + surrogate vs plain single-instance",
         "value": round(rate, 1), "unit": "solves/hr", "n_gpus": 1,
         "higher_is_better": True, "vs_baseline": None, "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": "channels of the batch family, lambda ~ U{64,128}, "
+        "config": {"workload": "channels of the batch family, lambda ~ U{%s}, "
                                "theta ~ U(30,150) deg, viscosity ratio ~ logU(0.1,10), "
-                               "default_rng(1612); bisection to 0.5 %, 3-decade plain "
-                               "bracket in Bo", "solves": n_eval},
+                               "default_rng(1612); bisection to 0.5 %%, 3-decade plain "
+                               "bracket in Bo" % args.lams, "solves": n_eval},
         "plain_single_solves_per_hour": round(plain_rate, 1),
         "speedup": round(rate / plain_rate, 2),
         "batched_plain_solves_per_hour": round(3600.0 * n_eval / t_bp, 1),
+        "gain_from_batching": round(t_single * n_eval / t_bp, 2),
+        "gain_from_surrogate": round(t_bp / t_bs, 2),
         "probes": {"batched_surrogate": sum(r["probes"] for r in bs),
                    "batched_plain": sum(r["probes"] for r in bp)},
-        # batched (args.storage) vs plain single-instance FP32 on the subset
-        "max_rel_diff_vs_single": round(agree, 5),
+        "by_lambda": by_lam,
+        # batched surrogate (args.storage) vs plain single-instance FP32
+        "single_checked": len(subset),
+        "max_rel_diff_vs_single": round(max(diffs), 5),
+        "within_1pct_vs_single": sum(1 for d in diffs if d <= 0.01),
         "surrogate_training": {"solves": len(train), "data_s": round(t_data, 1),
                                "fit_s": round(t_fit, 2), "val_rmse_log10": sur.sigma_val},
     }
@@ -349,13 +447,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tiling", default=None,
                     help="BX,STRIP for every instance (default: the library's default); "
                          "BX,BY,STRIP for --workload tube3d")
     ap.add_argument("--solves", type=int, default=128,
                     help="problems per set for --workload solves")
+    ap.add_argument("--train-solves", type=int, default=0,
+                    help="training problems for --workload solves (default: --solves)")
+    ap.add_argument("--lams", default="64,128",
+                    help="wavelengths of the --workload solves problems")
+    ap.add_argument("--single-per-lam", type=int, default=2,
+                    help="single-instance solves per wavelength for --workload solves")
     ap.add_argument("--reg-order", type=int, default=2, choices=(2, 3),
                     help="Hermite order of the regularization for the D2Q9 workloads")
     args = ap.parse_args()
@@ -428,6 +532,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu:
+        if args.workload == "batch" and args.reg_order == 2 and args.storage == "f32":
+            out["gpu_configs"] = gpu_configs_mlups()
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -61,6 +61,8 @@ def _lib():
         lib.orc_moments.argtypes = [pp, u8p, dp, dp, dp, dp, dp, dp]
         lib.orc_lattice.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                     dp, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_get_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -224,8 +226,11 @@ def step_once(params, mask, f):
 
 
 def threads_used():
-    """OpenMP threads the oracle's step loop will use (OMP_NUM_THREADS or cores)."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    if v:
-        return int(v.split(",")[0])
-    return os.cpu_count() or 1
+    """OpenMP threads the oracle's step loops will use."""
+    return int(_lib().orc_get_threads())
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP step loops (D2Q9 and D3Q19; timing only,
+    results do not depend on it)."""
+    _lib().orc_set_threads(int(n))

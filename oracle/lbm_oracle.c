@@ -39,6 +39,7 @@
  * geometry puts it at the price of exact mass conservation.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -70,6 +71,15 @@ typedef struct {
 } orc_params;
 
 /* ---- lattice constants, exported so tests can check them ------------------ */
+/* Threads of the OpenMP row loops (timing only: results do not depend on it). */
+void orc_set_threads(int n)
+{
+    if (n > 0)
+        omp_set_num_threads(n);
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
 void orc_lattice(int *cx, int *cy, double *w, int *opp)
 {
     for (int i = 0; i < Q; ++i) {
