@@ -83,10 +83,11 @@ def test_graph_replays_match_eager_steps(gpu_available):
 
 
 # Largest allowed |g_c(16-bit) / g_c(FP32) - 1|.  binary16 storage is held to
-# the 1 % target.  bfloat16 keeps 8 significand bits against binary16's 11,
-# so the rounding of the large force-shifted deviations on the interface is
-# 8 times coarser; it measured 1.08 % on the theta = 90 channel (one bisection
-# step of 0.5 % beyond binary16) and is held to 2 %, below the target's reach.
+# the 1 % target.  bfloat16 does NOT meet that target: it keeps 8 significand
+# bits against binary16's 11, so the rounding of the large force-shifted
+# deviations on the interface is 8 times coarser (1.08-1.36 % on these
+# channels, 40 % of a 48-channel set beyond 1 %).  Its bound of 2 % only
+# guards against regressions.
 CP_BOUND = {"f16": 0.01, "bf16": 0.02}
 
 

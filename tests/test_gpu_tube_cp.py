@@ -115,12 +115,11 @@ def test_tube_critical_forcing_vs_axisymmetric_young_laplace(gpu_available):
 
 def test_tube_critical_pressure_in_binary16_storage(gpu_available):
     """The tube solve with binary16 deviation storage against FP32 storage:
-    same problem, same rules; the critical forcings agree within 2 % (the 2-D
-    channels' bound for binary16 is 1 %; the tube's finer bracket steps and
-    the 3-D interface rounding are looser)."""
+    same problem, same rules, bisection to 0.25 %; the critical forcings agree
+    within the benchmark spec's 1 %."""
     from paper_1601_00918_amd import binding, binding3d as b3
     cfg = synth.config_tube(lam=32, r0=6.0, a=2.0, theta=120.0)
-    rules = dict(rel_tol=0.01, chunk_steps=500, min_steps=4000, still_chunks=3, verify_bracket=1)
+    rules = dict(rel_tol=0.0025, chunk_steps=500, min_steps=4000, still_chunks=3, verify_bracket=1)
     out = {}
     for storage in ("f32", "f16"):
         prob = b3.cp3_problem(cfg, 5e-5, 1e-3, SIGMA_3D, RHO_BAR, 2000, 40000)
@@ -128,7 +127,7 @@ def test_tube_critical_pressure_in_binary16_storage(gpu_available):
             [prob], binding.cp_options(storage=storage, **rules))[0]
     print({k: (v["g_crit"], v["flags"]) for k, v in out.items()})
     assert all(v["flags"] & ~binding._lib.CP_UNDECIDED == 0 for v in out.values())
-    assert abs(out["f16"]["g_crit"] / out["f32"]["g_crit"] - 1) <= 0.02
+    assert abs(out["f16"]["g_crit"] / out["f32"]["g_crit"] - 1) <= 0.01
 
 
 @pytest.mark.skipif(os.environ.get("LBM_STUDIES") != "1",
