@@ -148,6 +148,14 @@ typedef struct {
     const double* slugs; /* SLUG with n_slugs >= 1: host [n_slugs][2] pairs
                             (x0, length), length >= 0, read during lbm_init;
                             LBM_ERR_INVALID if null or out of range */
+    double width;        /* SLUG: width w of the initial oil/water interfaces along x.
+                            0: a step at each slug end.  w > 0: the hyperbolic-tangent
+                            profile the paper fits to interfaces (Sec. 3.1, Eq. 12):
+                            phi(x) = sum over slugs and their periodic images at
+                            +-nx of (tanh((x - x0 + 1/2) / w) - tanh((x - x0 - length
+                            + 1/2) / w)) / 2, clipped to [0, 1]; oil rho_lo +
+                            (rho_hi - rho_lo) phi, water rho_hi - (rho_hi - rho_lo) phi.
+                            Finite, >= 0, else LBM_ERR_INVALID. */
 } lbm_init_fields;
 
 /* Population storage format in HBM (arithmetic is always FP32).  The storage

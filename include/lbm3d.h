@@ -79,6 +79,8 @@ typedef struct {
     double cx, cy, cz, r; /* DROPLET */
     double x0, length;    /* SLUG */
     const double* slugs;  /* SLUG, n_slugs >= 1: host [n_slugs][2] (x0, length) */
+    double width;         /* SLUG: initial interface width along x, as in
+                             lbm_init_fields (0: a step) */
 } lbm3d_init_fields;
 
 typedef struct lbm3d_ctx lbm3d_ctx;

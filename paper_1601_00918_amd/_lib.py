@@ -70,7 +70,7 @@ class LbmInitFields(ctypes.Structure):
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("r", ctypes.c_double),
                 ("x0", ctypes.c_double), ("length", ctypes.c_double),
                 ("rho0", ctypes.POINTER(ctypes.c_double)),
-                ("slugs", ctypes.POINTER(ctypes.c_double))]
+                ("slugs", ctypes.POINTER(ctypes.c_double)), ("width", ctypes.c_double)]
 
 
 class LbmMonitor(ctypes.Structure):
@@ -121,7 +121,7 @@ class Lbm3dInitFields(ctypes.Structure):
                 ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double),
                 ("r", ctypes.c_double), ("x0", ctypes.c_double), ("length", ctypes.c_double),
-                ("slugs", ctypes.POINTER(ctypes.c_double))]
+                ("slugs", ctypes.POINTER(ctypes.c_double)), ("width", ctypes.c_double)]
 
 
 class Lbm3dCpProblem(ctypes.Structure):

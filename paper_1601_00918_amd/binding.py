@@ -54,14 +54,17 @@ def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0), reg_order=2):
 
 
 def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=0,
-                core_species=0, x0=0.0, length=0.0, rho0=None, slugs=None, _keep=None):
-    """slugs: optional list of (x0, length) pairs (several slugs in series)."""
+                core_species=0, x0=0.0, length=0.0, rho0=None, slugs=None, width=0.0,
+                _keep=None):
+    """slugs: optional list of (x0, length) pairs (several slugs in series);
+    width: tanh width of the slug interfaces (0: a step)."""
     s = LbmInitFields()
     s.kind = _INIT_KINDS[kind] if isinstance(kind, str) else int(kind)
     s.rho_hi, s.rho_lo = float(rho_hi), float(rho_lo)
     s.cx, s.cy, s.r = float(cx), float(cy), float(r)
     s.wall_rows, s.core_species = int(wall_rows), int(core_species)
     s.x0, s.length = float(x0), float(length)
+    s.width = float(width)
     if rho0 is not None:
         a = np.ascontiguousarray(rho0, dtype=np.float64)
         if _keep is not None:

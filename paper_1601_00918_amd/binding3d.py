@@ -42,13 +42,15 @@ def fluid3_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0, 0.0)):
 
 
 def init3_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, cz=0.0, r=0.0, x0=0.0,
-                 length=0.0, slugs=None, _keep=None):
-    """slugs: optional list of (x0, length) pairs (several slugs in series)."""
+                 length=0.0, slugs=None, width=0.0, _keep=None):
+    """slugs: optional list of (x0, length) pairs (several slugs in series);
+    width: tanh width of the slug interfaces (0: a step)."""
     s = Lbm3dInitFields()
     s.kind = _INIT_KINDS[kind] if isinstance(kind, str) else int(kind)
     s.rho_hi, s.rho_lo = float(rho_hi), float(rho_lo)
     s.cx, s.cy, s.cz, s.r = float(cx), float(cy), float(cz), float(r)
     s.x0, s.length = float(x0), float(length)
+    s.width = float(width)
     if slugs is not None:
         a = np.ascontiguousarray(slugs, dtype=np.float64).reshape(-1, 2)
         s.n_slugs = a.shape[0]

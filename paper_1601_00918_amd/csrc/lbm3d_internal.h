@@ -52,6 +52,7 @@ struct Init3Dev {
     double rho_hi, rho_lo;
     double cx, cy, cz, r;
     double x0[LBM_MAX_SLUGS], length[LBM_MAX_SLUGS];
+    double width;  // slug: tanh interface width (0: a step)
 };
 
 // Supported workgroup tiles (inner nodes per item in x and y).

@@ -557,6 +557,24 @@ __device__ double init_density3(const Init3Dev& ini, const Inst3Dev& P, int s, i
         break;
     }
     default: {  // slugs: (x - x0_k) mod nx < length_k for some k
+        if (ini.width > 0.0) {
+            // tanh interfaces at x0_k - 1/2 and x0_k + length_k - 1/2 (and
+            // their periodic images), the oil fraction phi clipped to [0, 1]
+            double phi = 0.0;
+            for (int k = 0; k < ini.n_slugs; ++k) {
+                double a = fmod(ini.x0[k], (double)P.nx);
+                if (a < 0.0)
+                    a += (double)P.nx;
+                for (int img = -1; img <= 1; ++img) {
+                    const double xx = (double)x + (double)img * (double)P.nx;
+                    phi += 0.5 * (tanh((xx - a + 0.5) / ini.width) -
+                                  tanh((xx - a - ini.length[k] + 0.5) / ini.width));
+                }
+            }
+            phi = fmin(fmax(phi, 0.0), 1.0);
+            const double span = ini.rho_hi - ini.rho_lo;
+            return s == 0 ? ini.rho_lo + span * phi : ini.rho_hi - span * phi;
+        }
         oil = false;
         for (int k = 0; k < ini.n_slugs; ++k) {
             double rel = fmod((double)x - ini.x0[k], (double)P.nx);

@@ -388,6 +388,9 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
         if (!lbm::slug_list(init->n_slugs, init->slugs, init->x0, init->length, slug_x0,
                             slug_len, n_slugs, err))
             return fail(LBM_ERR_INVALID, "lbm3d_init: %s", err.c_str());
+        if (!std::isfinite(init->width) || init->width < 0.0)
+            return fail(LBM_ERR_INVALID,
+                        "lbm3d_init: slug interface width must be finite and >= 0");
     }
     if (!(init->rho_hi > 0.0) || !(init->rho_lo > 0.0) ||
         !std::isfinite(init->rho_hi + init->rho_lo))
@@ -454,6 +457,7 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
         ini.x0[k] = init->kind == LBM3D_INIT_SLUG ? slug_x0[k] : init->x0;
         ini.length[k] = init->kind == LBM3D_INIT_SLUG ? slug_len[k] : init->length;
     }
+    ini.width = init->kind == LBM3D_INIT_SLUG ? init->width : 0.0;
     e = launch3_init(fmt, c->buf[0], c->P, c->runs_d, ini, c->stream);
     if (e != hipSuccess)
         return hip_bail(e, "init kernel launch");

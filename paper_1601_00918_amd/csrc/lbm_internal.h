@@ -84,6 +84,7 @@ struct InitDev {
     double rho_hi, rho_lo;
     double cx, cy, r;
     double x0[LBM_MAX_SLUGS], length[LBM_MAX_SLUGS];
+    double width;                  // SLUG: tanh interface width (0: a step)
 };
 
 // Export staging layout (doubles, one instance): [23][ny*nx]

@@ -553,6 +553,9 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
             std::string err;
             if (!slug_list(in.n_slugs, in.slugs, in.x0, in.length, xs, ls, cnt, err))
                 return fail(LBM_ERR_INVALID, "instance %d: %s", k, err.c_str());
+            if (!std::isfinite(in.width) || in.width < 0.0)
+                return fail(LBM_ERR_INVALID, "instance %d: slug interface width must be "
+                            "finite and >= 0", k);
         }
     }
     const Layout L = layout_of(geoms, n_inst, storage);
@@ -688,6 +691,7 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
             (void)slug_list(in.n_slugs, in.slugs, in.x0, in.length, ini.x0, ini.length,
                             ini.n_slugs, err);
         }
+        ini.width = in.kind == LBM_INIT_SLUG ? in.width : 0.0;
         int first = h.ny, last = -1;
         for (const Col& cc : h.cols)
             if (cc.lo <= cc.hi) {

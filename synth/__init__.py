@@ -90,16 +90,37 @@ def layers_field(nx, ny, wall_rows, mask, core_species=0, hi=RHO_HI, lo=RHO_LO):
     return rho
 
 
-def slug_field(nx, ny, x0, length, mask, hi=RHO_HI, lo=RHO_LO, slugs=None):
-    """Oil slug: fluid nodes with x in [x0, x0 + length) (periodic) are oil;
-    with slugs (a list of (x0, length) pairs) every listed slug is oil."""
-    x = np.arange(nx)[None, :] * np.ones((ny, 1), dtype=np.int64)
-    oil = np.zeros((ny, nx), dtype=bool)
+def slug_fraction(nx, x0, length, slugs=None, width=0.0):
+    """Oil fraction phi(x) [nx] of slugs along x: 1 on [x0, x0 + length)
+    (periodic), 0 elsewhere; with width > 0 the interfaces at x0 - 1/2 and
+    x0 + length - 1/2 (and their images at +-nx) are hyperbolic tangents of
+    that width, phi clipped to [0, 1]."""
+    x = np.arange(nx, dtype=np.float64)
+    phi = np.zeros(nx)
     for s0, sl in (slugs if slugs is not None else [(x0, length)]):
-        oil |= np.mod(x - s0, nx) < sl
+        if width > 0:
+            a = np.mod(float(s0), nx)
+            for img in (-1, 0, 1):
+                xx = x + img * nx
+                phi += 0.5 * (np.tanh((xx - a + 0.5) / width) -
+                              np.tanh((xx - a - sl + 0.5) / width))
+        else:
+            phi = np.maximum(phi, (np.mod(x - s0, nx) < sl).astype(np.float64))
+    return np.clip(phi, 0.0, 1.0)
+
+
+def slug_field(nx, ny, x0, length, mask, hi=RHO_HI, lo=RHO_LO, slugs=None, width=0.0):
+    """Oil slug: fluid nodes with x in [x0, x0 + length) (periodic) are oil;
+    with slugs (a list of (x0, length) pairs) every listed slug is oil; with
+    width > 0 the oil fraction follows slug_fraction's tanh interfaces."""
+    phi = slug_fraction(nx, x0, length, slugs, width)[None, :] * np.ones((ny, 1))
     rho = np.empty((2, ny, nx))
-    rho[0] = np.where(oil, hi, lo)
-    rho[1] = np.where(oil, lo, hi)
+    if width > 0:
+        rho[0] = lo + (hi - lo) * phi
+        rho[1] = hi - (hi - lo) * phi
+    else:  # exactly hi / lo
+        rho[0] = np.where(phi > 0, hi, lo)
+        rho[1] = np.where(phi > 0, lo, hi)
     rho *= mask[None, :, :]
     return rho
 
@@ -256,7 +277,7 @@ def rho0_of(cfg, mask=None):
         return layers_field(nx, ny, ini["wall_rows"], mask, ini.get("core_species", 0))
     if ini["kind"] == "slug":
         return slug_field(nx, ny, ini.get("x0", 0.0), ini.get("length", 0.0), mask,
-                          slugs=ini.get("slugs"))
+                          slugs=ini.get("slugs"), width=ini.get("width", 0.0))
     if ini["kind"] == "uniform":
         return np.stack([np.full((ny, nx), RHO_HI), np.full((ny, nx), RHO_LO)])
     raise ValueError(ini["kind"])
@@ -364,10 +385,16 @@ def rho03_of(cfg, mask=None):
         oil = (pd(x, ini["cx"], nx) ** 2 + pd(y, ini["cy"], ny) ** 2 +
                pd(z, ini["cz"], nz) ** 2) < ini["r"] ** 2
     elif ini["kind"] == "slug":
-        x = np.arange(nx)[None, None, :] * np.ones((nz, ny, 1), dtype=np.int64)
-        oil = np.zeros(mask.shape, dtype=bool)
-        for s0, sl in ini.get("slugs") or [(ini["x0"], ini["length"])]:
-            oil |= np.mod(x - s0, nx) < sl
+        width = ini.get("width", 0.0)
+        phi = slug_fraction(nx, ini["x0"], ini["length"], ini.get("slugs"), width)
+        phi = phi[None, None, :] * np.ones(mask.shape)
+        if width <= 0:
+            oil = phi > 0
+        else:
+            rho = np.empty((2,) + mask.shape)
+            rho[0] = RHO_LO + (RHO_HI - RHO_LO) * phi
+            rho[1] = RHO_HI - (RHO_HI - RHO_LO) * phi
+            return rho * mask[None]
     else:
         raise ValueError(ini["kind"])
     rho = np.empty((2,) + mask.shape)

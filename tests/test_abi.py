@@ -268,3 +268,12 @@ def test_stream_copy_validates_on_the_host():
     assert lib.lbm_stream_copy(ctypes.c_void_p((1 << 20) + 4), b, 64, 1 << 18, None) == 1
     assert lib.lbm_stream_copy(a, b, 64, 1000, None) == 1
     assert lib.lbm_stream_copy(a, b, 64, 0, None) == 1
+
+
+def test_slug_interface_width_validates_on_the_host():
+    g = [_geom()]
+    fl = [binding.fluid_struct((1.0, 1.0), -2.7)]
+    for w in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(_lib.LbmError) as e:
+            _try_init(g, fl, [binding.init_struct("slug", x0=4.0, length=20.0, width=w)])
+        assert e.value.status == 1 and "width" in str(e.value)

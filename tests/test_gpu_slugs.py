@@ -97,3 +97,47 @@ def test_two_slugs_in_phase_in_the_tube(gpu_available):
     assert all(r["flags"] & ~binding._lib.CP_UNDECIDED == 0 for r in res)
     assert abs(g2 / g1 - 2.0) <= 0.16
     assert g3 < 1.8 * g1
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_smooth_slug_start_matches_oracle(gpu_available, lattice):
+    """Slugs started with tanh interfaces (lbm_init_fields.width): the initial
+    populations equal the oracle's from the same synthetic field (FP64 tanh
+    on both sides, then one binary32 rounding), and the first steps follow
+    it within 2e-7 per step."""
+    if lattice == "d2q9":
+        from paper_1601_00918_amd import Simulation
+        from tests.gpu_util import oracle_lattice
+        cfg = synth.config_channel(lam=64, theta=90.0, tau=(1.5, 0.55), g=1e-5)
+        cfg["init"]["width"] = 2.0
+        L, mask, _ = oracle_lattice(cfg)
+        sim = Simulation([cfg])
+
+        def pops():
+            return sim.populations(0)
+    else:
+        from oracle import lbm3d as o3
+        from paper_1601_00918_amd.binding3d import C3, Simulation3D
+        cfg = synth.config_tube(lam=48, r0=14.0, a=6.0, nx=144, theta=90.0, tau=(1.5, 0.55),
+                                slug_len=46, slug_x0=4)
+        cfg["init"]["width"] = 2.0
+        mask = synth.mask3_of(cfg)
+        L = o3.Lattice3(o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                                   rho_s=cfg["rho_s"], g=cfg["g"]), mask,
+                        synth.rho03_of(cfg, mask))
+        sim = Simulation3D(cfg)
+        cx, cy, cz, _, _ = o3.lattice()
+        oc = np.stack([cx, cy, cz], axis=1)
+        perm = [int(np.nonzero((oc == c).all(axis=1))[0][0]) for c in C3]
+
+        def pops():
+            f = np.empty_like(L.f)
+            f[:, perm] = sim.populations()
+            return f
+    np.testing.assert_allclose(pops(), L.f, rtol=2.5e-7, atol=0)
+    for n in (1, 2, 5):
+        L.step(n - L.t)
+        sim.step(n - sim.t)
+        err = np.abs(pops() - L.f).max()
+        print(lattice, "t=%d max|df|=%.3e" % (n, err), flush=True)
+        assert err < 2e-7 * n

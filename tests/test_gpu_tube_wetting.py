@@ -101,7 +101,8 @@ def _angle_range(radius, nominal):
     return min(vals), max(vals)
 
 
-def _paper_tube_study(D, nominal, target, tau=(1.0, 1.0), label="", positions=4, ramp=True):
+def _paper_tube_study(D, nominal, target, tau=(1.0, 1.0), label="", positions=4, ramp=True,
+                      width=0.0):
     """The paper's tube at neck radius D (three periods over L = 18 D, radius D
     at the neck and 2.5 D at the widest), slugs of about `target` D^3 at four
     positions a quarter wavelength apart; 40,000 unforced steps, the 90 %
@@ -110,7 +111,8 @@ def _paper_tube_study(D, nominal, target, tau=(1.0, 1.0), label="", positions=4,
     volumes, the critical Bo and the Young-Laplace values without and with the
     angle spread, with the measured 3-D angle range of the wall potentials.
     With ramp=False the critical Bo is the bisection's alone (to 2 %), and
-    positions limits the slug positions studied."""
+    positions limits the slug positions studied; width > 0 starts the slugs
+    with tanh interfaces of that width instead of a step."""
     from oracle import young_laplace as yl
     from paper_1601_00918_amd import binding, binding3d as b3
     sig, rho_bar = 0.195, 1.03
@@ -121,7 +123,10 @@ def _paper_tube_study(D, nominal, target, tau=(1.0, 1.0), label="", positions=4,
     for j in range(positions):
         x0 = D // 2 + (lam // 4) * j
         n = int(np.searchsorted(np.cumsum(np.roll(col, -x0)), target * D ** 3)) + 1
-        cfgs.append(synth.config_tube(slug_x0=x0, slug_len=n, **base))
+        cfg = synth.config_tube(slug_x0=x0, slug_len=n, **base)
+        if width > 0:
+            cfg["init"]["width"] = float(width)
+        cfgs.append(cfg)
     L = cfgs[0]["nx"]
     to_g = sig / (rho_bar * L * D)
     vols = []
@@ -234,5 +239,17 @@ def test_paper_tube_viscosity_ratio_one_position(gpu_available):
     test_paper_tube_viscosity_ratio_study (LBM_STUDIES=1)."""
     r = _paper_tube_study(8, 30.0, 56.0, tau=(1.5, 0.55), label="water-wet", positions=1,
                           ramp=False)
+    assert all(f & ~1 == 0 for f in r["flags"])
+    assert np.all(np.abs(r["bo"] / r["bo0"] - 1) <= 0.25)
+
+
+def test_paper_tube_viscosity_ratio_neutral_smooth_start(gpu_available):
+    """Table 5 analogue for the neutral wall at the paper's tau pair (1.5,
+    0.55): from a sharp slug this case turns non-physical within a few steps
+    (in the FP64 oracle as on the GPU); started with tanh interfaces of width
+    2 (the profile the paper fits, Eq. 12) it runs.  One position, bisection
+    to 2 %, against the axisymmetric Young-Laplace value: within 25 %."""
+    r = _paper_tube_study(8, 90.0, 58.0, tau=(1.5, 0.55), label="intermediate", positions=1,
+                          ramp=False, width=2.0)
     assert all(f & ~1 == 0 for f in r["flags"])
     assert np.all(np.abs(r["bo"] / r["bo0"] - 1) <= 0.25)
