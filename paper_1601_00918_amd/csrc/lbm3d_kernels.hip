@@ -109,6 +109,7 @@ __device__ __forceinline__ Mom3 moments19(const float* f)
 // w_i / (2 T0^2) H_i : Pi^neq of the species' own non-equilibrium flux
 // Pi^neq = Pi - rho T0 I - j j / rho; with w_i = W_i / 36 it is
 // W_i / 8 (c_i c_i : Pi^neq - tr Pi^neq / 3).
+template <bool FASTDIV>
 __device__ __forceinline__ void collide19(const Mom3& m, float vx, float vy, float vz, float om,
                                           float (&out)[kQ])
 {
@@ -133,7 +134,8 @@ __device__ __forceinline__ void collide19(const Mom3& m, float vx, float vy, flo
     const float gxzm = om * (0.125f * (sxz - 2.0f * nxz));
     const float gyzp = om * (0.125f * (syz + 2.0f * nyz));
     const float gyzm = om * (0.125f * (syz - 2.0f * nyz));
-    const float b5 = m.rho / 36.0f;  // correctly rounded
+    // correctly rounded (FP32), within about half a unit (16-bit formats)
+    const float b5 = FASTDIV ? div36_fast(m.rho) : m.rho / 36.0f;
     const float b1 = 2.0f * b5;
     const float b0 = 12.0f * b5;
     const float vsq15 = 1.5f * (vx * vx + vy * vy + vz * vz);
@@ -415,7 +417,9 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
             }
             const float ro = prev[0].rho, rw = prev[1].rho;
             const float rho = ro + rw;
-            const float inv = 1.0f / rho;  // correctly rounded: u_mix carries no bias
+            // correctly rounded (or, 16-bit formats, within about half a unit):
+            // u_mix carries no bias
+            const float inv = S::kRef ? rcp_fast(rho) : 1.0f / rho;
             const float ux = (prev[0].jx + prev[1].jx) * inv;
             const float uy = (prev[0].jy + prev[1].jy) * inv;
             const float uz = (prev[0].jz + prev[1].jz) * inv;
@@ -426,14 +430,14 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
                 float out[2][kQ];
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
-                    collide19(prev[s], ux + G36 * sx[s] + P.g[0], uy + G36 * sy[s] + P.g[1],
-                              uz + G36 * sz[s] + P.g[2], om, out[s]);
+                    collide19<S::kRef>(prev[s], ux + G36 * sx[s] + P.g[0],
+                                       uy + G36 * sy[s] + P.g[1], uz + G36 * sz[s] + P.g[2],
+                                       om, out[s]);
                 // Streaming stores: read back only by the next step.
                 char* dst = obase + PB * ((uint32_t)((zc * ny + y) * rs) + (uint32_t)x);
                 if constexpr (S::kRef) {
-                    const uint32_t key = ((uint32_t)((zc * ny + y) * nx + x)) << 1;
-                    const uint32_t rnd[2] = {lowbias32(key ^ seed_h),
-                                             lowbias32((key | 1u) ^ seed_h)};
+                    uint32_t rnd[2];
+                    split_rnd(lowbias32((uint32_t)((zc * ny + y) * nx + x) ^ seed_h), rnd);
                     const float rho36[2] = {ro, rw};
                     encode_node19<S>(out, rho36, rnd, dst, plane);
                 } else {

@@ -210,7 +210,7 @@ struct ColG {
 // momentum flux Pi^neq = Pi - rho T0 I - j j / rho, the second moment of
 // f - f^eq(rho, j / rho) in closed form (the species' own equilibrium); on
 // D2Q9 it takes five distinct values (rest, axis x, axis y, two diagonals).
-template <bool R3>
+template <bool R3, bool FASTDIV>
 __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy, float om,
                                                 bool reg3, float (&out)[9])
 {
@@ -226,7 +226,9 @@ __device__ __forceinline__ void collide_species(const Mom& m, float vx, float vy
     const float gd = tr * (1.0f / 12.0f);
     const float g5 = om * (gd + 0.25f * nxy);
     const float g6 = om * (gd - 0.25f * nxy);
-    const float b5 = m.rho / 36.0f;  // correctly rounded: no bias in w_i rho
+    // correctly rounded (FP32 storage), or within about half a unit (the
+    // 16-bit formats, FASTDIV): either way no systematic bias in w_i rho
+    const float b5 = FASTDIV ? div36_fast(m.rho) : m.rho / 36.0f;
     const float b1 = 4.0f * b5;
     const float b0 = 16.0f * b5;
     const float vsq15 = 1.5f * (vx * vx + vy * vy);
@@ -487,15 +489,30 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                 }
             }
             if (S::kRef) {
+                // Reference density of each pull's source node (x - c_i, r -
+                // c_y,i): a constant offset from this column in one of three
+                // ring rows; the node's own after bounce-back.
                 const uint32_t bbm = bb_next;
+                const float2* rrow[3] = {rref + ((r + 1) & 3) * RW + tid + 2,   // c_y = -1
+                                         rref + (r & 3) * RW + tid + 2,         // c_y = 0
+                                         rref + ((r - 1) & 3) * RW + tid + 2};  // c_y = +1
+                const float2 Rown = rrow[1][0];
+                if (__ballot(bbm != 0u) == 0) {  // no bounce-back in the wave
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const bool bb = (bbm >> i) & 1u;
-                    const int sl = bb ? (r & 3) : ((r - kCy[i]) & 3);
-                    const int cl = bb ? tid + 2 : tid + 2 - kCx[i];
-                    const float2 R = rref[sl * RW + cl];
-                    raw[i] = kW36[i] * (R.x + raw[i]);
-                    raw[9 + i] = kW36[i] * (R.y + raw[9 + i]);
+                    for (int i = 0; i < 9; ++i) {
+                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
+                        raw[i] = kW36[i] * (Rs.x + raw[i]);
+                        raw[9 + i] = kW36[i] * (Rs.y + raw[9 + i]);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
+                        const bool bb = (bbm >> i) & 1u;
+                        const float Ro = bb ? Rown.x : Rs.x, Rw = bb ? Rown.y : Rs.y;
+                        raw[i] = kW36[i] * (Ro + raw[i]);
+                        raw[9 + i] = kW36[i] * (Rw + raw[9 + i]);
+                    }
                 }
             }
             cur[0] = moments9(raw);
@@ -606,7 +623,9 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
             }
             const float ro = prev[0].rho, rw = prev[1].rho;
             const float rho = ro + rw;
-            const float inv = 1.0f / rho;  // correctly rounded: u_mix carries no bias
+            // correctly rounded (or, 16-bit formats, within about half a unit):
+            // u_mix carries no bias
+            const float inv = S::kRef ? rcp_fast(rho) : 1.0f / rho;
             const float ux = (prev[0].jx + prev[1].jx) * inv;
             const float uy = (prev[0].jy + prev[1].jy) * inv;
             const float taum = 0.5f + (ro * P.tau_h[0] + rw * P.tau_h[1]) * inv;
@@ -618,15 +637,14 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                 for (int s = 0; s < 2; ++s) {
                     const float vx = ux + G36 * sx[s] + P.g[0];
                     const float vy = uy + G36 * sy[s] + P.g[1];
-                    collide_species<EXT>(prev[s], vx, vy, om, P.reg3 != 0, out[s]);
+                    collide_species<EXT, S::kRef>(prev[s], vx, vy, om, P.reg3 != 0, out[s]);
                 }
                 // Streaming stores: the populations are read back only by the
                 // next step, long after they would have left L2.
                 char* dst = obase + PB * ((uint32_t)(rrc * RS) + (uint32_t)x);
                 if constexpr (S::kRef) {
-                    const uint32_t key = ((uint32_t)(rrc * P.nx + x)) << 1;
-                    const uint32_t rnd[2] = {lowbias32(key ^ seed_h),
-                                             lowbias32((key | 1u) ^ seed_h)};
+                    uint32_t rnd[2];
+                    split_rnd(lowbias32((uint32_t)(rrc * P.nx + x) ^ seed_h), rnd);
                     const float rho36[2] = {ro, rw};
                     encode_node<S>(out, rho36, rnd, dst, plane);
                 } else {

@@ -67,21 +67,26 @@ struct Store<F16Tag> {
     }
     __device__ static float val(uint32_t b) { return h2f(b); }
     __device__ static uint32_t rne(float v) { return f2h_rn(v); }
-    // Stochastic rounding to binary16: add uniform random bits below the
-    // target precision to the magnitude and truncate (exact conversion after).
-    __device__ static uint32_t sr(float v, uint32_t rnd)
+    // Stochastic rounding to binary16 with 16 uniform random bits r16: add
+    // random bits below the target precision to the magnitude and truncate
+    // (exact conversion after).  Where more than 16 bits lie below the last
+    // place (deep subnormals) the random offset is r16 shifted up, so the
+    // probability of rounding up is quantised to 2^-16.
+    __device__ static uint32_t sr(float v, uint32_t r16)
     {
         const uint32_t u = __float_as_uint(v);
         const uint32_t sign = u & 0x80000000u;
         uint32_t a = u & 0x7fffffffu;
         const int e = (int)(a >> 23) - 127;
         if (e >= -14) {  // binary16 normal range: 13 bits below the last place
-            a = (a + (rnd & 0x1fffu)) & ~0x1fffu;
-        } else if (e >= -24) {  // subnormal: the last place is 2^-24
-            const uint32_t m = (1u << (uint32_t)(-1 - e)) - 1u;
-            a = (a + (rnd & m)) & ~m;
+            a = (a + (r16 & 0x1fffu)) & ~0x1fffu;
+        } else if (e >= -24) {  // subnormal: the last place is 2^-24, k bits below it
+            const int k = -1 - e;
+            const uint32_t m = (1u << (uint32_t)k) - 1u;
+            const uint32_t rk = k > 16 ? (r16 << (uint32_t)(k - 16)) : (r16 & m);
+            a = (a + rk) & ~m;
         } else {  // below 2^-24: 0 or 2^-24 with probability |v| / 2^-24
-            a = (float)(rnd >> 8) * 0x1p-24f < __uint_as_float(a) * 0x1p24f ? 0x33800000u : 0u;
+            a = (float)r16 * 0x1p-16f < __uint_as_float(a) * 0x1p24f ? 0x33800000u : 0u;
         }
         return f2h_rn(__uint_as_float(sign | a));
     }
@@ -107,9 +112,10 @@ struct Store<BF16Tag> {
         const uint32_t u = __float_as_uint(v);
         return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
     }
-    __device__ static uint32_t sr(float v, uint32_t rnd)
+    // Stochastic rounding with 16 uniform random bits r16.
+    __device__ static uint32_t sr(float v, uint32_t r16)
     {
-        return (__float_as_uint(v) + (rnd & 0xffffu)) >> 16;
+        return (__float_as_uint(v) + (r16 & 0xffffu)) >> 16;
     }
 };
 
@@ -124,6 +130,31 @@ __device__ __forceinline__ uint32_t lowbias32(uint32_t x)
     x *= 0x846ca68bu;
     x ^= x >> 16;
     return x;
+}
+
+// Two independent 16-bit random values for the stochastic rounding of both
+// species at one node: the halves of one hash of the node's key.
+__device__ __forceinline__ void split_rnd(uint32_t h, uint32_t (&rnd)[2])
+{
+    rnd[0] = h & 0xffffu;
+    rnd[1] = h >> 16;
+}
+
+// x / 36 and 1 / x to within about half a unit in the last place, in three
+// operations each (a product or the hardware reciprocal, then one
+// residual-correction step with FMA), for the 16-bit formats' collisions,
+// which are bound by instruction issue.  Inputs are positive densities
+// (normal numbers), so no scaling for denormals or overflow is needed.
+__device__ __forceinline__ float div36_fast(float x)
+{
+    constexpr float r = 1.0f / 36.0f;
+    const float q = x * r;
+    return fmaf(fmaf(-36.0f, q, x), r, q);
+}
+__device__ __forceinline__ float rcp_fast(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
 }
 
 __device__ __forceinline__ int wrapi(int a, int n)
