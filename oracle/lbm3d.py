@@ -19,7 +19,10 @@ class Orc3Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("periodic_yz", ctypes.c_int32), ("tau", ctypes.c_double * 2),
                 ("G", ctypes.c_double), ("rho_s", ctypes.c_double * 2),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("wall_interp", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("wall_yc", ctypes.c_double),
+                ("wall_zc", ctypes.c_double), ("wall_r0", ctypes.c_double),
+                ("wall_a", ctypes.c_double), ("wall_lam", ctypes.c_double)]
 
 
 _LIB = None
@@ -43,6 +46,8 @@ def _lib():
         lib.orc3_run.restype = ctypes.c_int64
         lib.orc3_init.argtypes = [pp, u8p, dp, dp]
         lib.orc3_moments.argtypes = [pp, u8p, dp, dp, dp, dp, dp, dp]
+        lib.orc3_wall_fraction.argtypes = [pp] + [ctypes.c_int] * 4
+        lib.orc3_wall_fraction.restype = ctypes.c_double
         _LIB = lib
     return _LIB
 
@@ -81,7 +86,10 @@ def regularize(f, feq):
 
 class Params3:
     def __init__(self, nx, ny, nz, tau=(1.0, 1.0), G=0.0, rho_s=(0.0, 0.0),
-                 g=(0.0, 0.0, 0.0), periodic_yz=False):
+                 g=(0.0, 0.0, 0.0), periodic_yz=False, wall=None):
+        """wall = (y_c, z_c, r0, a, lambda): interpolated walls on the tube
+        (y - y_c)^2 + (z - z_c)^2 = (r0 + a cos(2 pi x / lambda))^2; None:
+        half-way bounce-back at the mask's solid nodes."""
         self.c = Orc3Params()
         self.c.nx, self.c.ny, self.c.nz = int(nx), int(ny), int(nz)
         self.c.periodic_yz = 1 if periodic_yz else 0
@@ -90,6 +98,10 @@ class Params3:
         self.c.rho_s[0], self.c.rho_s[1] = float(rho_s[0]), float(rho_s[1])
         for a in range(3):
             self.c.g[a] = float(g[a])
+        if wall is not None:
+            self.c.wall_interp = 1
+            (self.c.wall_yc, self.c.wall_zc, self.c.wall_r0, self.c.wall_a,
+             self.c.wall_lam) = (float(v) for v in wall)
 
     @property
     def shape(self):
@@ -97,6 +109,12 @@ class Params3:
 
     def ref(self):
         return ctypes.byref(self.c)
+
+
+def wall_fraction(params, x, y, z, i):
+    """Fraction of the link from fluid node (x, y, z) along c_i at which it
+    leaves the tube of params' interpolated walls."""
+    return _lib().orc3_wall_fraction(params.ref(), int(x), int(y), int(z), int(i))
 
 
 def step_once(params, mask, f):

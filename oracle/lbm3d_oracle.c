@@ -24,6 +24,12 @@
  *   mask [nz][ny][nx]          1 = fluid
  * x is always periodic; y and z are periodic when periodic_yz != 0, otherwise a
  * node outside the box counts as solid.
+ *
+ * Walls: half-way bounce-back at solid links (default), or, with wall_interp,
+ * the analytic sinusoidal tube wall (y - yc)^2 + (z - zc)^2 = r(x)^2,
+ * r(x) = r0 + a cos(2 pi x / lambda), at its sub-lattice position by linear
+ * interpolated bounce-back with the mass returned through the rest population
+ * (orc3_step_interp), as the D2Q9 oracle does for its channel walls.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +64,11 @@ typedef struct {
     double G;
     double rho_s[2];
     double g[3];
+    /* Interpolated tube walls (wall_interp != 0): axis (wall_yc, wall_zc),
+     * radius wall_r0 + wall_a cos(2 pi x / wall_lam). */
+    int32_t wall_interp;
+    int32_t reserved;
+    double wall_yc, wall_zc, wall_r0, wall_a, wall_lam;
 } orc3_params;
 
 void orc3_lattice(int *cx, int *cy, int *cz, double *w, int *opp)
@@ -200,11 +211,17 @@ static void gather3(const orc3_params *p, const uint8_t *mask, const double *f,
     }
 }
 
+static int orc3_step_interp(const orc3_params *p, const uint8_t *mask, const double *f_in,
+                            double *f_out, double *rho_work);
+
 /* One step, f_in (time t) -> f_out (time t + 1).  Returns the number of fluid
  * nodes whose densities were not finite and positive. */
+
 int orc3_step(const orc3_params *p, const uint8_t *mask, const double *f_in, double *f_out,
               double *rho_work)
 {
+    if (p->wall_interp)
+        return orc3_step_interp(p, mask, f_in, f_out, rho_work);
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const size_t n = (size_t)nx * ny * nz;
     int bad = 0;
@@ -242,6 +259,129 @@ int orc3_step(const orc3_params *p, const uint8_t *mask, const double *f_in, dou
                     }
                 }
             }
+    return bad;
+}
+
+/* Inside the analytic tube (the voxelisation's own expression, at any point). */
+static int tube_inside(const orc3_params *p, double X, double Y, double Z)
+{
+    const double r = p->wall_r0 + p->wall_a * cos(6.283185307179586476925286766559 * X /
+                                                 p->wall_lam);
+    const double dy = Y - p->wall_yc, dz = Z - p->wall_zc;
+    return dy * dy + dz * dz < r * r;
+}
+
+/* Fraction q in (0, 1] of the link from fluid node (x, y, z) along c_i at
+ * which it leaves the tube: 60 halvings of the link, keeping the first point
+ * found outside. */
+double orc3_wall_fraction(const orc3_params *p, int x, int y, int z, int i)
+{
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        const double t = 0.5 * (lo + hi);
+        if (tube_inside(p, x + t * CX3[i], y + t * CY3[i], z + t * CZ3[i]))
+            lo = t;
+        else
+            hi = t;
+    }
+    return hi;
+}
+
+/* Collision of one fluid node (the same arithmetic as orc3_step), returning
+ * the post-collision populations of both species. */
+static int collide3(const orc3_params *p, const uint8_t *mask, const double *f_in,
+                    const double *rho_work, int x, int y, int z, double post[2][Q3])
+{
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    const size_t k = index3(p, x, y, z);
+    node3 st;
+    gather3(p, mask, f_in, rho_work, x, y, z, &st);
+    const int bad = (!(st.rho[0] > 0.0) || !(st.rho[1] > 0.0) ||
+                     !isfinite(st.rho[0] + st.rho[1])) ? 1 : 0;
+    const double taum = tau_mix3(p, st.rho[0], st.rho[1]);
+    for (int s = 0; s < 2; ++s) {
+        double fl[Q3], feq_own[Q3], feq_shift[Q3], fneq[Q3];
+        for (int i = 0; i < Q3; ++i)
+            fl[i] = f_in[((size_t)s * Q3 + i) * n + k];
+        orc3_equilibrium(st.rho[s], st.u[0] + st.F[s][0] / st.rho[s],
+                         st.u[1] + st.F[s][1] / st.rho[s], st.u[2] + st.F[s][2] / st.rho[s],
+                         feq_shift);
+        orc3_equilibrium(st.rho[s], st.j[s][0] / st.rho[s], st.j[s][1] / st.rho[s],
+                         st.j[s][2] / st.rho[s], feq_own);
+        orc3_regularize(fl, feq_own, fneq);
+        for (int i = 0; i < Q3; ++i)
+            post[s][i] = feq_shift[i] + (1.0 - 1.0 / taum) * fneq[i];
+    }
+    return bad;
+}
+
+/* One step with interpolated tube walls: collide every node, then stream; a
+ * population leaving fluid node x along c_i towards a wall met at the fraction
+ * q of the link returns as f_opp(i)(x) by the linear interpolated bounce-back
+ * of Bouzidi, Firdaouss and Lallemand (2001):
+ *   q <  1/2: 2q f*_i(x) + (1 - 2q) f*_i(x - c_i)   (f*_i(x) if x - c_i is solid)
+ *   q >= 1/2: f*_i(x) / (2q) + (1 - 1/(2q)) f*_opp(i)(x)
+ * and what the blends add beyond half-way bounce-back is taken from the node's
+ * rest population, so each species keeps its mass. */
+static int orc3_step_interp(const orc3_params *p, const uint8_t *mask, const double *f_in,
+                            double *f_out, double *rho_work)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const size_t n = (size_t)nx * ny * nz;
+    int bad = 0;
+    orc3_densities(p, mask, f_in, rho_work);
+    double *post = (double *)calloc(2 * Q3 * n, sizeof(double));
+    if (!post)
+        return -1;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t k = index3(p, x, y, z);
+                if (!mask[k])
+                    continue;
+                double fp[2][Q3];
+                bad += collide3(p, mask, f_in, rho_work, x, y, z, fp);
+                for (int s = 0; s < 2; ++s)
+                    for (int i = 0; i < Q3; ++i)
+                        post[((size_t)s * Q3 + i) * n + k] = fp[s][i];
+            }
+    memset(f_out, 0, sizeof(double) * 2 * Q3 * n);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t k = index3(p, x, y, z);
+                if (!mask[k])
+                    continue;
+                for (int s = 0; s < 2; ++s) {
+                    double dm = 0.0;
+                    for (int i = 0; i < Q3; ++i) {
+                        const double v = post[((size_t)s * Q3 + i) * n + k];
+                        const int xn = x + CX3[i], yn = y + CY3[i], zn = z + CZ3[i];
+                        if (fluid3(p, mask, xn, yn, zn)) {
+                            f_out[((size_t)s * Q3 + i) * n + index3(p, xn, yn, zn)] = v;
+                            continue;
+                        }
+                        const double q = orc3_wall_fraction(p, x, y, z, i);
+                        double back;
+                        if (q < 0.5) {
+                            const int xb = x - CX3[i], yb = y - CY3[i], zb = z - CZ3[i];
+                            back = fluid3(p, mask, xb, yb, zb)
+                                       ? 2.0 * q * v + (1.0 - 2.0 * q) *
+                                             post[((size_t)s * Q3 + i) * n + index3(p, xb, yb, zb)]
+                                       : v;
+                        } else {
+                            back = v / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) *
+                                                       post[((size_t)s * Q3 + opposite3(i)) * n + k];
+                        }
+                        f_out[((size_t)s * Q3 + opposite3(i)) * n + k] = back;
+                        dm += back - v;
+                    }
+                    f_out[((size_t)s * Q3 + 0) * n + k] -= dm;
+                }
+            }
+    free(post);
     return bad;
 }
 

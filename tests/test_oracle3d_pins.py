@@ -1,8 +1,9 @@
 """Pins of the D3Q19 oracle (oracle/lbm3d_oracle.c) against what mathematics
 and an independent implementation fix: lattice isotropy, equilibrium and
 regularization moments, a numpy transcription of the step on tiny lattices,
-exact mass conservation in a closed tube, and the Laplace law for 3-D
-droplets."""
+exact mass conservation in a closed tube, the Laplace law for 3-D droplets,
+and the interpolated tube walls (link fractions in closed form, second-order
+Hagen-Poiseuille, mass kept)."""
 import itertools
 
 import numpy as np
@@ -173,3 +174,104 @@ def test_flat_interface_equal_bulk_pressures():
         return T0 * r.sum() + G * T0 * r[0] * r[1]
 
     assert abs(flipped(ro) / flipped(rw) - 1) > 1e-4
+
+
+# ---- interpolated (sub-lattice) tube walls -----------------------------------
+def test_tube_wall_fraction_geometry():
+    """Link fractions against the straight tube's closed form along the axes
+    and a direct root of the sinusoidal wall along a face diagonal."""
+    from scipy.optimize import brentq
+    import math
+    cx, cy, cz, _, _ = o3.lattice()
+    R, side = 5.3, 13
+    yc = zc = 0.5 * (side - 1)
+    p = o3.Params3(4, side, side, wall=(yc, zc, R, 0.0, 1.0))
+    mask = synth.tube_mask(4, side, side, 1.0, R, 0.0)
+    checked = 0
+    for z, y in itertools.product(range(side), range(side)):
+        if not mask[z, y, 0]:
+            continue
+        for i in (3, 4, 5, 6):          # +-y, +-z
+            if mask[z + cz[i], y + cy[i], 0]:
+                continue
+            if cy[i]:
+                want = math.sqrt(R * R - (z - zc) ** 2) - cy[i] * (y - yc)
+            else:
+                want = math.sqrt(R * R - (y - yc) ** 2) - cz[i] * (z - zc)
+            assert 0.0 < want <= 1.0
+            assert o3.wall_fraction(p, 1, y, z, i) == pytest.approx(want, abs=1e-12)
+            checked += 1
+    assert checked > 20
+    cfg = synth.config_tube(lam=32, r0=6.0, a=2.0)
+    ny, nz = cfg["ny"], cfg["nz"]
+    yc, zc = 0.5 * (ny - 1), 0.5 * (nz - 1)
+    ps = o3.Params3(cfg["nx"], ny, nz, wall=(yc, zc, cfg["r0"], cfg["a"], cfg["lam"]))
+    m = synth.mask3_of(cfg)
+    checked = 0
+    for x in (3, 11, 20):
+        for z, y in itertools.product(range(nz), range(ny)):
+            if not m[z, y, x]:
+                continue
+            for i in (7, 11, 16):       # (1,1,0), (1,0,1), (0,-1,-1)
+                xn = (x + cx[i]) % cfg["nx"]
+                if m[z + cz[i], y + cy[i], xn]:
+                    continue
+
+                def gap(t):
+                    X, Y, Z = x + t * cx[i], y + t * cy[i], z + t * cz[i]
+                    r = cfg["r0"] + cfg["a"] * math.cos(2 * math.pi * X / cfg["lam"])
+                    return math.hypot(Y - yc, Z - zc) - r
+                want = brentq(gap, 0.0, 1.0, xtol=1e-15)
+                assert o3.wall_fraction(ps, x, y, z, i) == pytest.approx(want, abs=1e-12)
+                checked += 1
+    assert checked > 20
+
+
+def test_interpolated_tube_walls_give_hagen_poiseuille():
+    """A single fluid (G = 0, uniform densities) driven along a straight tube
+    whose radius R falls between nodes: the steady profile is Hagen-Poiseuille,
+    u = g (R^2 - rho^2) / (4 nu), vanishing at the analytic wall.  With
+    interpolated walls the error falls by about four when R doubles (second
+    order); the staircase of half-way bounce-back on the same nodes does not
+    converge (its effective radius varies around the circle) and is over ten
+    times further off at the finer radius."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3.0
+    errs = {}
+    for R in (4.3, 8.6):
+        g = 1e-5 * (4.3 / R) ** 2
+        side = int(2 * R + 3)
+        mask = synth.tube_mask(2, side, side, 1.0, R, 0.0)
+        yc = zc = 0.5 * (side - 1)
+        rho0 = np.stack([np.full(mask.shape, 0.5)] * 2) * mask
+        zz, yy = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+        want = g * (R * R - (yy - yc) ** 2 - (zz - zc) ** 2) / (4.0 * nu)
+        fl = mask[:, :, 0].astype(bool)
+        for interp in (True, False):
+            p = o3.Params3(2, side, side, tau=(tau, tau), G=0.0, g=(g, 0.0, 0.0),
+                           wall=(yc, zc, R, 0.0, 1.0) if interp else None)
+            L = o3.Lattice3(p, mask, rho0)
+            L.step(int(3000 * (R / 4.3) ** 2))
+            u = L.moments()["u"][0][:, :, 0]
+            errs[R, interp] = np.abs(u[fl] - want[fl]).max() / want.max()
+    print({k: "%.2e" % v for k, v in errs.items()})
+    assert errs[4.3, True] < 0.025 and errs[8.6, True] < 0.005
+    assert 3.3 < errs[4.3, True] / errs[8.6, True] < 5.5
+    assert errs[8.6, False] > 10 * errs[8.6, True]
+
+
+def test_interpolated_tube_walls_keep_each_species_mass():
+    """Two-component slug with wall potentials in a sinusoidal tube: what the
+    interpolated walls add returns through the rest population, so each
+    species' mass stays constant to rounding."""
+    cfg = synth.config_tube(lam=32, r0=6.0, a=2.0, theta=60.0, g=2e-4)
+    mask = synth.mask3_of(cfg)
+    yc, zc = 0.5 * (cfg["ny"] - 1), 0.5 * (cfg["nz"] - 1)
+    p = o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                   rho_s=cfg["rho_s"], g=cfg["g"],
+                   wall=(yc, zc, cfg["r0"], cfg["a"], cfg["lam"]))
+    L = o3.Lattice3(p, mask, synth.rho03_of(cfg, mask))
+    m0 = L.moments()["mon"][:2]
+    L.step(200)
+    m1 = L.moments()["mon"][:2]
+    assert np.allclose(m1, m0, rtol=1e-12, atol=0)
