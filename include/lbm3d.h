@@ -54,6 +54,14 @@ typedef struct {
                              must stay below 4 GiB */
     double lambda, r0, a; /* LBM3D_GEOM_TUBE only: lambda > 0, r0 > 0, a >= 0 */
     const uint8_t* mask;  /* LBM3D_GEOM_MASK only, copied during lbm3d_init */
+    int32_t wall_interp;  /* LBM3D_GEOM_TUBE: 1 places the wall at its analytic
+                             position between the nodes by linear interpolated
+                             bounce-back (Bouzidi, Firdaouss and Lallemand 2001),
+                             with what the blends add taken from the node's rest
+                             population so each species keeps its mass; the link
+                             fractions are computed once at init, in FP64, and
+                             kept in the workspace.  0: half-way bounce-back on
+                             the voxelised tube.  Any storage format. */
 } lbm3d_geom;
 
 typedef struct {
@@ -126,7 +134,8 @@ lbm_status lbm3d_fluid_mask(lbm3d_ctx* ctx, uint8_t* mask);
 
 /* Tiling of the step kernel: one workgroup advances a tile of bx x by nodes
  * (x, y) through a strip of strip_planes planes along z.  (bx, by) is one of
- * (32, 16) (default), (64, 8), (32, 8); strip_planes >= 4 (default 8).
+ * (32, 16) (default; (32, 8) with interpolated walls), (64, 8), (32, 8);
+ * strip_planes >= 4 (default 8).
  * Results do not depend on the tiling (bit for bit).  Synchronises. */
 lbm_status lbm3d_set_tiling(lbm3d_ctx* ctx, int32_t bx, int32_t by, int32_t strip_planes);
 lbm_status lbm3d_get_tiling(const lbm3d_ctx* ctx, int32_t* bx, int32_t* by,

@@ -108,7 +108,8 @@ class LbmCpResult(ctypes.Structure):
 class Lbm3dGeom(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("lam", ctypes.c_double), ("r0", ctypes.c_double),
-                ("a", ctypes.c_double), ("mask", ctypes.POINTER(ctypes.c_uint8))]
+                ("a", ctypes.c_double), ("mask", ctypes.POINTER(ctypes.c_uint8)),
+                ("wall_interp", ctypes.c_int32)]
 
 
 class Lbm3dFluid(ctypes.Structure):

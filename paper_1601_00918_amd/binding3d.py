@@ -17,11 +17,13 @@ _INIT_KINDS = {"uniform": INIT3_UNIFORM, "droplet": INIT3_DROPLET, "slug": INIT3
 _STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
 
-def geom3_struct(kind, nx, ny, nz, lam=0.0, r0=0.0, a=0.0, mask=None, _keep=None):
+def geom3_struct(kind, nx, ny, nz, lam=0.0, r0=0.0, a=0.0, mask=None, _keep=None,
+                 wall_interp=False):
     g = Lbm3dGeom()
     g.kind = _GEOM_KINDS[kind] if isinstance(kind, str) else int(kind)
     g.nx, g.ny, g.nz = int(nx), int(ny), int(nz)
     g.lam, g.r0, g.a = float(lam), float(r0), float(a)
+    g.wall_interp = 1 if wall_interp else 0
     if mask is not None:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         assert m.shape == (nz, ny, nx)
@@ -65,7 +67,8 @@ def structs3_from_config(cfg, keep=None, rho_hi=None, rho_lo=None):
     """(geom, fluid, init) structs from a 3-D workload dict (box3d, tube or mask)."""
     kind = cfg["kind"]
     geom = geom3_struct(kind, cfg["nx"], cfg["ny"], cfg["nz"], cfg.get("lam", 0.0),
-                        cfg.get("r0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep)
+                        cfg.get("r0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep,
+                        wall_interp=cfg.get("wall_interp", False))
     fluid = fluid3_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)),
                           cfg.get("g", (0, 0, 0)))
     ini = dict(cfg["init"])

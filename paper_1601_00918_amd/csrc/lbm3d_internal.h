@@ -9,6 +9,15 @@
 
 namespace lbm3 {
 
+// Interpolated walls, per (x, y) column with fluid run [lo, hi]: the nodes
+// a <= z < b have no wall link (every neighbour x - c_i fluid); each other
+// node owns a row of link fractions, node z < a at row base + z - lo and
+// node z >= b at row base + (a - lo) + (z - b).
+struct WallCol {
+    uint32_t base;
+    uint32_t ab;  // a | b << 16
+};
+
 // The lattice as the kernels see it.  Lattice row (y, z) is the contiguous
 // block of planes at pair index ((z * ny + y) * rs); plane i holds, for every
 // x, the pair (oil, water) of direction i:
@@ -25,6 +34,9 @@ struct Inst3Dev {
     float rho_s[2];    // wall potentials
     float g[3];        // body acceleration
     double Gd;         // G in double (pressure export)
+    // Interpolated tube walls (null: half-way bounce-back everywhere).
+    const WallCol* wcol;  // [ny][nx]
+    const float* wq;      // [rows][18]: link fraction of pulled direction i at i - 1
 };
 
 // A work item: one workgroup collides the nodes x0 .. x0 + BXI - 1,

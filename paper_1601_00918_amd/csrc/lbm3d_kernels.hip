@@ -202,7 +202,20 @@ __device__ __forceinline__ bool in_run(uint32_t run, int z)
     return (unsigned)(z - lo) < (unsigned)(hi1 - lo);
 }
 
-template <int BXI, int BYI, int MODE, bool PER, typename T>
+// Interpolated walls: the linear interpolated bounce-back of Bouzidi,
+// Firdaouss and Lallemand (2001) for a population pulled in direction i from a
+// solid node, given its half-way value f*_opp(i)(x), the wall's fraction q of
+// the link from x along -c_i, and
+//   q <  1/2: f*_opp(i)(x + c_i) (the half-way value again if that node is solid),
+//   q >= 1/2: f*_i(x).
+// (q = 1/2 gives the half-way value itself.)
+__device__ __forceinline__ float ibb_blend(float q, float half_way, float extra)
+{
+    return q < 0.5f ? (2.0f * q) * half_way + (1.0f - 2.0f * q) * extra
+                    : half_way * (0.5f / q) + (1.0f - 0.5f / q) * extra;
+}
+
+template <int BXI, int BYI, int MODE, bool PER, typename T, bool WALL>
 __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __restrict__ fout,
                                        const Inst3Dev& P, const Item3& it, int item_idx,
                                        const uint32_t* __restrict__ runs,
@@ -250,6 +263,16 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
                     run[a][b] = runs[yy * nx + xx];
             }
         }
+
+    // Interpolated walls: this column's entry of the link-fraction table.
+    WallCol wc{0u, 0u};
+    int wlo = 0;
+    if constexpr (WALL) {
+        if (run[1][1] != kEmptyRun) {
+            wc = P.wcol[y * nx + x];
+            wlo = (int)(run[1][1] & 0xffffu);
+        }
+    }
 
     const int64_t n_nodes = (int64_t)nx * ny * nz;
     double macc[kMon3Width];
@@ -369,6 +392,87 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
                     const float2 R = rref[sl * REFN + cl];
                     raw[i] = kW36[i] * (R.x + raw[i]);
                     raw[kQ + i] = kW36[i] * (R.y + raw[kQ + i]);
+                }
+            }
+            if constexpr (WALL) {
+                // Blend every wall link (waves holding a node next to the
+                // wall only).  The node's 18 link fractions come in one batch
+                // of loads, then the blend partners in two batches of nine
+                // directions, branch-free (lanes without that link load their
+                // own slot and keep the pulled value), so a wave waits on
+                // memory three times per plane.  What the blends add, summed
+                // over i = 1..18 in order, is taken from the rest population,
+                // so each species keeps its mass.  Frame and inner threads run
+                // the same code, so a density is the same whichever workgroup
+                // computes it.
+                const uint32_t bbm = bb_next;
+                if (__ballot(bbm != 0u) != 0) {
+                    const int wa = (int)(wc.ab & 0xffffu), wb = (int)(wc.ab >> 16);
+                    const int row = (int)wc.base + (r < wa ? r - wlo : (wa - wlo) + (r - wb));
+                    float qv[kQ - 1];
+                    {
+                        const float2* __restrict__ q2 = reinterpret_cast<const float2*>(
+                            P.wq + (int64_t)(bbm ? row : 0) * (kQ - 1));
+#pragma unroll
+                        for (int k = 0; k < (kQ - 1) / 2; ++k) {
+                            const float2 t = q2[k];
+                            qv[2 * k] = t.x;
+                            qv[2 * k + 1] = t.y;
+                        }
+                    }
+                    const int zs[3] = {(r - 1) * ny, r * ny, (r + 1) * ny};
+                    const int ys[3] = {ym, y, yp};
+                    const int xs[3] = {xm, x, xp};
+                    float dm0 = 0.0f, dm1 = 0.0f;
+#pragma unroll
+                    for (int g0 = 1; g0 < kQ; g0 += 9) {
+                        Pair ex[9];
+                        bool far[9];
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) {
+                            const int i = g0 + t;
+                            const int cx = kCx[i], cy = kCy[i], cz = kCz[i];
+                            const bool wall = (bbm >> i) & 1u;
+                            // q < 1/2: f*_opp(i) at x + c_i, if that node is fluid
+                            far[t] = wall && qv[i - 1] < 0.5f &&
+                                     in_run(run[1 + cy][1 + cx], r + cz);
+                            const uint32_t o_far =
+                                PB * ((uint32_t)((zs[1 + cz] + ys[1 + cy]) * rs) +
+                                      (uint32_t)(kOpp[i] * P.pitch) + (uint32_t)xs[1 + cx]);
+                            const uint32_t o_own = PB * ((uint32_t)((zs[1] + y) * rs) +
+                                                         (uint32_t)(i * P.pitch) + (uint32_t)x);
+                            ex[t] = S::load(base + (far[t] ? o_far : o_own));
+                        }
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) {
+                            const int i = g0 + t;
+                            const int cx = kCx[i], cy = kCy[i], cz = kCz[i];
+                            const bool wall = (bbm >> i) & 1u;
+                            const float q = qv[i - 1];
+                            float eo, ew;
+                            S::unpack(ex[t], eo, ew);
+                            if (S::kRef) {
+                                const int sl = far[t] ? ((r + cz) & 3) : (r & 3);
+                                const int cl = far[t] ? (ty + 1 + cy) * RXW + tx + 1 + cx
+                                                      : (ty + 1) * RXW + tx + 1;
+                                const float2 R = rref[sl * REFN + cl];
+                                eo = kW36[i] * (R.x + eo);
+                                ew = kW36[i] * (R.y + ew);
+                            }
+                            // q < 1/2 with a solid partner: the half-way value
+                            const bool keep = !far[t] && q < 0.5f;
+                            eo = keep ? raw[i] : eo;
+                            ew = keep ? raw[kQ + i] : ew;
+                            const float bo = wall ? ibb_blend(q, raw[i], eo) : raw[i];
+                            const float bw = wall ? ibb_blend(q, raw[kQ + i], ew) : raw[kQ + i];
+                            dm0 += bo - raw[i];
+                            dm1 += bw - raw[kQ + i];
+                            raw[i] = bo;
+                            raw[kQ + i] = bw;
+                        }
+                    }
+                    raw[0] -= dm0;
+                    raw[kQ] -= dm1;
                 }
             }
             cur[0] = moments19(raw);
@@ -510,7 +614,7 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
     }
 }
 
-template <int BXI, int BYI, int MODE, typename T>
+template <int BXI, int BYI, int MODE, typename T, bool WALL>
 __global__ void __launch_bounds__((Tile<BXI, BYI>::NT))
 step3_kernel(const void* __restrict__ fin, void* __restrict__ fout, const Inst3Dev P,
              const Item3* __restrict__ items, const uint32_t* __restrict__ runs,
@@ -522,12 +626,15 @@ step3_kernel(const void* __restrict__ fin, void* __restrict__ fout, const Inst3D
     __shared__ double red[TL::NT / 64 * kMon3Width];
     const int item_idx = remap_xcd((int)blockIdx.x, (int)gridDim.x);
     const Item3 it = items[item_idx];
-    if (P.periodic)
-        march3<BXI, BYI, MODE, true, T>(fin, fout, P, it, item_idx, runs, partial, stage, seed,
-                                        ring, rref, red);
+    if constexpr (WALL)  // a tube: never periodic in y and z
+        march3<BXI, BYI, MODE, false, T, true>(fin, fout, P, it, item_idx, runs, partial, stage,
+                                               seed, ring, rref, red);
+    else if (P.periodic)
+        march3<BXI, BYI, MODE, true, T, false>(fin, fout, P, it, item_idx, runs, partial, stage,
+                                               seed, ring, rref, red);
     else
-        march3<BXI, BYI, MODE, false, T>(fin, fout, P, it, item_idx, runs, partial, stage,
-                                         seed, ring, rref, red);
+        march3<BXI, BYI, MODE, false, T, false>(fin, fout, P, it, item_idx, runs, partial,
+                                                stage, seed, ring, rref, red);
 }
 
 __global__ void mon3_reduce_kernel(const double* __restrict__ partial, int n_items,
@@ -596,7 +703,9 @@ __device__ double init_density3(const Init3Dev& ini, const Inst3Dev& P, int s, i
 // Rest equilibrium f_i = w_i rho0, placed where the first pull reads it: the
 // slot (x, i) is read by node x + c_i when that node is fluid, otherwise by x
 // itself after bounce-back.  16-bit formats: rho0(reader) - R(x) to nearest
-// even, R(x) = binary16(rho0(x)).
+// even, R(x) = binary16(rho0(x)).  Interpolated walls: the slots the first
+// pull blends are set so that the blends, and the rest population after the
+// mass return, give w_i rho0(x) too (below).
 template <typename T>
 __global__ void init3_kernel(void* __restrict__ A, const Inst3Dev P,
                              const uint32_t* __restrict__ runs, Init3Dev ini)
@@ -615,6 +724,17 @@ __global__ void init3_kernel(void* __restrict__ A, const Inst3Dev P,
     };
     if (!fluid(x, y, z))
         return;
+    // Link fractions of this node (interpolated walls, nodes with a wall link).
+    const float* qrow = nullptr;
+    if (P.wq) {
+        const uint32_t run = runs[y * P.nx + x];
+        const WallCol wc = P.wcol[y * P.nx + x];
+        const int lo = (int)(run & 0xffffu);
+        const int wa = (int)(wc.ab & 0xffffu), wb = (int)(wc.ab >> 16);
+        if (z < wa || z >= wb)
+            qrow = P.wq + (int64_t)((int)wc.base + (z < wa ? z - lo : (wa - lo) + (z - wb))) *
+                              (kQ - 1);
+    }
     char* node = reinterpret_cast<char*>(A) +
                  (int64_t)S::kPair * (((int64_t)z * P.ny + y) * P.rs + x);
     const int64_t plane = (int64_t)S::kPair * P.pitch;
@@ -641,8 +761,41 @@ __global__ void init3_kernel(void* __restrict__ A, const Inst3Dev P,
             yr = y;
             zr = z;
         }
-        const double rho_o = init_density3(ini, P, 0, xr, yr, zr);
-        const double rho_w = init_density3(ini, P, 1, xr, yr, zr);
+        double rho_o = init_density3(ini, P, 0, xr, yr, zr);
+        double rho_w = init_density3(ini, P, 1, xr, yr, zr);
+        if (qrow && i > 0 && xr == x && yr == y && zr == z) {
+            // x reads this slot as the half-way value of j = opp(i); with the
+            // wall at q >= 1/2 the first pull blends it with slot (x, j),
+            // which holds w rho0(x + c_j) for the node x + c_j that pulls it.
+            // Store the value that makes the blend w_i rho0(x).  (For
+            // q < 1/2 the partner already holds w_i rho0(x).)
+            const int j = kOpp[i];
+            const float q = qrow[j - 1];
+            const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j], zo = z + kCz[j];
+            if (q >= 0.5f && fluid(xo, yo, zo)) {
+                const double two_q = 2.0 * (double)q;
+                rho_o = two_q * rho_o - (two_q - 1.0) * init_density3(ini, P, 0, xo, yo, zo);
+                rho_w = two_q * rho_w - (two_q - 1.0) * init_density3(ini, P, 1, xo, yo, zo);
+            }
+        }
+        if (qrow && i == 0) {
+            // The first pull takes from the rest population what those blends
+            // add to their half-way values, (2q - 1) w_j (rho0(x + c_j) -
+            // rho0(x)) per link: store it in advance, so that the pulled rest
+            // population is w_0 rho0(x).
+            const double ro = rho_o, rw = rho_w;
+            for (int j = 1; j < kQ; ++j) {
+                if (fluid(wrapi(x - kCx[j], P.nx), y - kCy[j], z - kCz[j]))
+                    continue;
+                const float q = qrow[j - 1];
+                const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j], zo = z + kCz[j];
+                if (q >= 0.5f && fluid(xo, yo, zo)) {
+                    const double c = (2.0 * (double)q - 1.0) * (kW36[j] / kW36[0]);
+                    rho_o += c * (init_density3(ini, P, 0, xo, yo, zo) - ro);
+                    rho_w += c * (init_density3(ini, P, 1, xo, yo, zo) - rw);
+                }
+            }
+        }
         if constexpr (S::kRef)
             *reinterpret_cast<uint32_t*>(node + i * plane) =
                 S::rne((float)(rho_o - (double)R[0])) |
@@ -652,28 +805,41 @@ __global__ void init3_kernel(void* __restrict__ A, const Inst3Dev P,
     }
 }
 
+template <int BXI, int BYI, int MODE, typename T>
+void launch_mode(const void* fin, void* fout, const Inst3Dev& P, const Item3* items,
+                 int n_items, const uint32_t* runs, double* partial, double* stage,
+                 uint32_t seed, hipStream_t stream)
+{
+    const dim3 grid(n_items), block(Tile<BXI, BYI>::NT);
+    if (P.wq)
+        step3_kernel<BXI, BYI, MODE, T, true>
+            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+    else
+        step3_kernel<BXI, BYI, MODE, T, false>
+            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+}
+
 template <int BXI, int BYI, typename T>
 hipError_t launch_tile(int mode, const void* fin, void* fout, const Inst3Dev& P,
                        const Item3* items, int n_items, const uint32_t* runs, double* partial,
                        double* stage, uint32_t seed, hipStream_t stream)
 {
-    const dim3 grid(n_items), block(Tile<BXI, BYI>::NT);
     switch (mode) {
     case kStep:
-        step3_kernel<BXI, BYI, kStep, T>
-            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+        launch_mode<BXI, BYI, kStep, T>(fin, fout, P, items, n_items, runs, partial, stage,
+                                        seed, stream);
         break;
     case kStepMon:
-        step3_kernel<BXI, BYI, kStepMon, T>
-            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+        launch_mode<BXI, BYI, kStepMon, T>(fin, fout, P, items, n_items, runs, partial, stage,
+                                           seed, stream);
         break;
     case kMonOnly:
-        step3_kernel<BXI, BYI, kMonOnly, T>
-            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+        launch_mode<BXI, BYI, kMonOnly, T>(fin, fout, P, items, n_items, runs, partial, stage,
+                                           seed, stream);
         break;
     case kExport:
-        step3_kernel<BXI, BYI, kExport, T>
-            <<<grid, block, 0, stream>>>(fin, fout, P, items, runs, partial, stage, seed);
+        launch_mode<BXI, BYI, kExport, T>(fin, fout, P, items, n_items, runs, partial, stage,
+                                          seed, stream);
         break;
     default:
         return hipErrorInvalidValue;

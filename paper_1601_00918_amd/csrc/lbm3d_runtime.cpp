@@ -52,11 +52,11 @@ int64_t max_items(const lbm3d_geom& g)
 
 struct Layout3 {
     size_t buf_bytes, off_buf[2], off_snap, off_items, off_runs, off_partial, off_mon,
-        off_stage, total;
+        off_stage, off_wcol, off_wq, total;
     int64_t n_items_max;
 };
 
-Layout3 layout_of(const lbm3d_geom& g, int storage_and_opts)
+Layout3 layout_of(const lbm3d_geom& g, int storage_and_opts, int64_t wall_rows)
 {
     const int storage = storage_and_opts & 0xff;
     Layout3 L{};
@@ -81,6 +81,14 @@ Layout3 layout_of(const lbm3d_geom& g, int storage_and_opts)
     o = align_up(o + sizeof(double) * kMon3Width, kAlign);
     L.off_stage = o;
     o = align_up(o + sizeof(double) * kExport3Fields * (size_t)nodes, kAlign);
+    L.off_wcol = o;
+    L.off_wq = o;
+    if (g.wall_interp) {
+        o = align_up(o + sizeof(WallCol) * (size_t)g.nx * g.ny, kAlign);
+        L.off_wq = o;
+        // at least one row: lanes without a wall link read row 0
+        o = align_up(o + sizeof(float) * 18 * (size_t)std::max<int64_t>(wall_rows, 1), kAlign);
+    }
     L.total = o;
     return L;
 }
@@ -101,11 +109,23 @@ lbm_status check_geom(const lbm3d_geom* g, int storage)
                     g->nx, g->ny, g->nz);
     switch (g->kind) {
     case LBM3D_GEOM_BOX:
+    case LBM3D_GEOM_MASK:
+        if (g->wall_interp != 0)
+            return fail(LBM_ERR_UNSUPPORTED,
+                        "lbm3d: interpolated walls need the analytic tube geometry");
+        break;
+    default:
+        break;
+    }
+    switch (g->kind) {
+    case LBM3D_GEOM_BOX:
         return LBM_OK;
     case LBM3D_GEOM_TUBE:
         if (!(g->lambda > 0.0) || !(g->r0 > 0.0) || !(g->a >= 0.0) ||
             !std::isfinite(g->lambda + g->r0 + g->a))
             return fail(LBM_ERR_INVALID, "lbm3d: tube needs lambda > 0, r0 > 0, a >= 0");
+        if (g->wall_interp != 0 && g->wall_interp != 1)
+            return fail(LBM_ERR_INVALID, "lbm3d: wall_interp must be 0 or 1");
         return LBM_OK;
     case LBM3D_GEOM_MASK:
         if (!g->mask)
@@ -185,6 +205,99 @@ lbm_status voxelise(const lbm3d_geom& g, std::vector<uint32_t>& runs)
             runs[(size_t)y * g.nx + x] = lo >= 0 ? pack_run(lo, hi) : kEmptyRun;
         }
     return LBM_OK;
+}
+
+constexpr int kCx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy3[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz3[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// Interpolated tube walls: the column table (WallCol) from the fluid runs,
+// and, with `wq`, the link fractions of every node that has a wall link.
+// Node (x, y, z) pulls direction i from x - c_i; where that node is solid the
+// row holds, at i - 1, the fraction q in (0, 1] of the link from the node
+// along -c_i at which it leaves the tube (the voxelisation's own expression),
+// in FP64 by 60 halvings of the link, keeping the first point found outside.
+// Returns the number of rows.
+int64_t wall_table(const lbm3d_geom& g, const std::vector<uint32_t>& runs,
+                   std::vector<WallCol>* wcol, std::vector<float>* wq)
+{
+    auto run_at = [&](int x, int y) -> uint32_t {
+        if (y < 0 || y >= g.ny)
+            return kEmptyRun;
+        return runs[(size_t)y * g.nx + (x + g.nx) % g.nx];
+    };
+    const double yc = 0.5 * (g.ny - 1), zc = 0.5 * (g.nz - 1);
+    auto inside = [&](double X, double Y, double Z) {
+        const double r = g.r0 + g.a * std::cos(2.0 * M_PI * X / g.lambda);
+        const double dy = Y - yc, dz = Z - zc;
+        return dy * dy + dz * dz < r * r;
+    };
+    if (wcol)
+        wcol->assign((size_t)g.nx * g.ny, WallCol{0u, 0u});
+    if (wq)
+        wq->clear();
+    int64_t rows = 0;
+    for (int y = 0; y < g.ny; ++y)
+        for (int x = 0; x < g.nx; ++x) {
+            const uint32_t r = runs[(size_t)y * g.nx + x];
+            if (r == kEmptyRun)
+                continue;
+            const int lo = (int)(r & 0xffffu), hi = (int)(r >> 16) - 1;
+            int A = lo, B = hi;  // nodes whose every neighbour is fluid
+            for (int i = 1; i < 19; ++i) {
+                const uint32_t rn = run_at(x - kCx3[i], y - kCy3[i]);
+                if (rn == kEmptyRun) {
+                    A = hi + 1;
+                    break;
+                }
+                A = std::max(A, (int)(rn & 0xffffu) + kCz3[i]);
+                B = std::min(B, (int)(rn >> 16) - 1 + kCz3[i]);
+            }
+            int a = A, b = B + 1;
+            if (A > B)
+                a = b = hi + 1;
+            if (wcol)
+                (*wcol)[(size_t)y * g.nx + x] =
+                    WallCol{(uint32_t)rows, (uint32_t)a | ((uint32_t)b << 16)};
+            if (wq) {
+                for (int z = lo; z <= hi; ++z) {
+                    if (z >= a && z < b)
+                        continue;
+                    for (int i = 1; i < 19; ++i) {
+                        const uint32_t rn = run_at(x - kCx3[i], y - kCy3[i]);
+                        const int zs = z - kCz3[i];
+                        const bool src_fluid = rn != kEmptyRun && zs >= (int)(rn & 0xffffu) &&
+                                               zs < (int)(rn >> 16);
+                        double q = 1.0;
+                        if (!src_fluid) {
+                            double tlo = 0.0, thi = 1.0;
+                            for (int it = 0; it < 60; ++it) {
+                                const double t = 0.5 * (tlo + thi);
+                                if (inside(x - t * kCx3[i], y - t * kCy3[i], z - t * kCz3[i]))
+                                    tlo = t;
+                                else
+                                    thi = t;
+                            }
+                            q = thi;
+                        }
+                        wq->push_back((float)q);
+                    }
+                }
+            }
+            rows += (a - lo) + (hi + 1 - b);
+        }
+    return rows;
+}
+
+// Rows of the link-fraction table (0 without interpolated walls).
+int64_t wall_rows_of(const lbm3d_geom& g)
+{
+    if (!g.wall_interp)
+        return 0;
+    std::vector<uint32_t> runs;
+    if (voxelise(g, runs) != LBM_OK)
+        return 0;
+    return wall_table(g, runs, nullptr, nullptr);
 }
 
 Inst3Dev make_inst(const lbm3d_geom& g, int storage)
@@ -356,7 +469,7 @@ lbm_status lbm3d_required_bytes(const lbm3d_geom* geom, int32_t storage, size_t*
         return st;
     if (storage & ~(0xff | LBM_OPT_SNAPSHOT))
         return fail(LBM_ERR_INVALID, "lbm3d_required_bytes: unknown option bits 0x%x", storage);
-    *bytes = layout_of(*geom, storage).total;
+    *bytes = layout_of(*geom, storage, wall_rows_of(*geom)).total;
     return LBM_OK;
 }
 
@@ -395,7 +508,14 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     if (!(init->rho_hi > 0.0) || !(init->rho_lo > 0.0) ||
         !std::isfinite(init->rho_hi + init->rho_lo))
         return fail(LBM_ERR_INVALID, "lbm3d_init: densities must be finite and > 0");
-    const Layout3 L = layout_of(*geom, storage);
+    std::vector<uint32_t> runs;
+    st = voxelise(*geom, runs);
+    if (st != LBM_OK)
+        return st;
+    std::vector<WallCol> wcol;
+    std::vector<float> wq;
+    const int64_t wall_rows = geom->wall_interp ? wall_table(*geom, runs, &wcol, &wq) : 0;
+    const Layout3 L = layout_of(*geom, storage, wall_rows);
     if (!device_workspace)
         return fail(LBM_ERR_INVALID, "lbm3d_init: workspace is NULL");
     if (workspace_bytes < L.total)
@@ -412,11 +532,11 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     c->geom.mask = nullptr;
     c->L = L;
     c->stream = (hipStream_t)hip_stream;
-    st = voxelise(*geom, c->runs);
-    if (st != LBM_OK) {
-        delete c;
-        return st;
-    }
+    c->runs = std::move(runs);
+    // The interpolated-wall step holds more live values per node; the
+    // 32 x 8 tile (two waves per SIMD, 256 registers) keeps them in registers.
+    if (geom->wall_interp)
+        c->tile = 2;
     c->P = make_inst(*geom, fmt);
     fill_fluid(c->P, *fluid);
     char* ws = (char*)device_workspace;
@@ -444,6 +564,19 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
                        hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess)
         return hip_bail(e, "hipMemcpyAsync");
+    if (geom->wall_interp) {
+        WallCol* wcol_d = (WallCol*)(ws + L.off_wcol);
+        float* wq_d = (float*)(ws + L.off_wq);
+        e = hipMemcpyAsync(wcol_d, wcol.data(), sizeof(WallCol) * wcol.size(),
+                           hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && !wq.empty())
+            e = hipMemcpyAsync(wq_d, wq.data(), sizeof(float) * wq.size(),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess)
+            return hip_bail(e, "hipMemcpyAsync");
+        c->P.wcol = wcol_d;
+        c->P.wq = wq_d;
+    }
     Init3Dev ini{};
     ini.kind = init->kind;
     ini.rho_hi = init->rho_hi;

@@ -339,8 +339,10 @@ def tube_mask(nx, ny, nz, lam, r0, a):
 
 
 def config_tube(lam=64, r0=10.0, a=4.0, nx=None, ny=None, nz=None, theta=90.0,
-                tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug_len=None, slug_x0=None):
-    """Sinusoidal tube (three wavelengths unless nx is given) with an oil slug."""
+                tau=(1.0, 1.0), g=0.0, G=G_DEFAULT, slug_len=None, slug_x0=None,
+                wall_interp=False):
+    """Sinusoidal tube (three wavelengths unless nx is given) with an oil slug;
+    wall_interp: walls at their analytic position (interpolated bounce-back)."""
     nx = 3 * lam if nx is None else nx
     side = int(2 * (r0 + a) + 2)
     ny = side if ny is None else ny
@@ -349,7 +351,8 @@ def config_tube(lam=64, r0=10.0, a=4.0, nx=None, ny=None, nz=None, theta=90.0,
     slug_x0 = lam // 4 if slug_x0 is None else slug_x0
     return dict(name="tube", nx=nx, ny=ny, nz=nz, kind="tube", lam=float(lam), r0=float(r0),
                 a=float(a), tau=tau, G=G, rho_s=wall_potentials_for_angle(theta),
-                g=(g, 0.0, 0.0), theta=theta, init=dict(kind="slug", x0=slug_x0, length=slug_len))
+                g=(g, 0.0, 0.0), theta=theta, init=dict(kind="slug", x0=slug_x0, length=slug_len),
+                wall_interp=bool(wall_interp))
 
 
 def config_box3d(n=32, r=8.0, tau=(1.0, 1.0), G=G_DEFAULT, kind="droplet"):

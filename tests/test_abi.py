@@ -190,6 +190,44 @@ def test_lbm3d_required_bytes_and_validation():
     assert _lib.load().lbm3d_required_bytes(ctypes.byref(g), 9, ctypes.byref(n)) == 6
 
 
+def test_lbm3d_interpolated_wall_table_size_and_validation():
+    """The workspace grows by the column table (8 bytes per (x, y) column) and
+    one row of 18 FP32 link fractions per fluid node with a solid neighbour,
+    counted here from the mask with numpy; interpolated walls exist only for
+    the analytic tube."""
+    import synth
+    from paper_1601_00918_amd import binding3d as b3
+    cx, cy, cz = (np.array(v) for v in zip(*b3.C3))
+    for lam, r0, a in ((32.0, 6.0, 2.0), (64.0, 9.3, 3.7)):
+        nx, side = int(3 * lam), int(2 * (r0 + a) + 2)
+        plain = b3.lbm3d_required_bytes(b3.geom3_struct("tube", nx, side, side, lam=lam,
+                                                        r0=r0, a=a), "f16")
+        interp = b3.lbm3d_required_bytes(b3.geom3_struct("tube", nx, side, side, lam=lam,
+                                                         r0=r0, a=a, wall_interp=True), "f16")
+        m = synth.tube_mask(nx, side, side, lam, r0, a).astype(bool)
+        padded = np.zeros((side + 2, side + 2, nx), dtype=bool)
+        padded[1:-1, 1:-1] = m
+        walled = np.zeros_like(m)
+        for i in range(1, 19):   # source x - c_i solid
+            src = np.roll(padded, int(cx[i]), axis=2)[1 - cz[i]:side + 1 - cz[i],
+                                                       1 - cy[i]:side + 1 - cy[i]]
+            walled |= m & ~src
+        rows = int(walled.sum())
+        up = lambda v: (v + 255) // 256 * 256
+        assert interp - plain == up(8 * nx * side) + up(72 * rows), (rows, interp - plain)
+    for kind in ("box", "mask"):
+        g = b3.geom3_struct(kind, 8, 8, 8, mask=np.ones((8, 8, 8), np.uint8),
+                            wall_interp=True)
+        with pytest.raises(_lib.LbmError) as e:
+            b3.lbm3d_required_bytes(g)
+        assert e.value.status == 6 and "tube" in str(e.value)
+    g = b3.geom3_struct("tube", 96, 18, 18, lam=32.0, r0=6.0, a=2.0)
+    g.wall_interp = 2
+    with pytest.raises(_lib.LbmError) as e:
+        b3.lbm3d_required_bytes(g)
+    assert e.value.status == 1
+
+
 def test_lbm3d_critical_pressure_validates_on_the_host():
     """Rejected before any device work (the workspace pointer is never used)."""
     import synth
