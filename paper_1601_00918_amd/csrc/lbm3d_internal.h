@@ -68,9 +68,9 @@ struct Init3Dev {
 };
 
 // Supported workgroup tiles (inner nodes per item in x and y).
-constexpr int kTiles3 = 3;
-constexpr int kTileBx[kTiles3] = {32, 64, 32};
-constexpr int kTileBy[kTiles3] = {16, 8, 8};
+constexpr int kTiles3 = 4;
+constexpr int kTileBx[kTiles3] = {32, 64, 32, 16};
+constexpr int kTileBy[kTiles3] = {16, 8, 8, 12};
 
 // Launchers (lbm3d_kernels.hip); all enqueue on `stream` and return the launch
 // status.  tile indexes kTileBx / kTileBy.

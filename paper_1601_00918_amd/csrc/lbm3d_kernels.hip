@@ -853,7 +853,7 @@ hipError_t launch_t(int tile, int mode, const void* fin, void* fout, const Inst3
                     double* stage, uint32_t seed, hipStream_t stream)
 {
     static_assert(kTileBx[0] == 32 && kTileBy[0] == 16 && kTileBx[1] == 64 && kTileBy[1] == 8 &&
-                      kTileBx[2] == 32 && kTileBy[2] == 8,
+                      kTileBx[2] == 32 && kTileBy[2] == 8 && kTileBx[3] == 16 && kTileBy[3] == 12,
                   "tile table and instantiations disagree");
     switch (tile) {
     case 0:
@@ -865,6 +865,9 @@ hipError_t launch_t(int tile, int mode, const void* fin, void* fout, const Inst3
     case 2:
         return launch_tile<32, 8, T>(mode, fin, fout, P, items, n_items, runs, partial, stage,
                                      seed, stream);
+    case 3:
+        return launch_tile<16, 12, T>(mode, fin, fout, P, items, n_items, runs, partial, stage,
+                                      seed, stream);
     default:
         return hipErrorInvalidValue;
     }

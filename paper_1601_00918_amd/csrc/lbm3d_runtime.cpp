@@ -333,7 +333,7 @@ struct lbm3d_ctx {
     Layout3 L{};
     std::vector<uint32_t> runs;
     std::vector<Item3> items;
-    int tile = 0, strip = kDefaultStrip;
+    int tile = 3, strip = kDefaultStrip;
     char* buf[2] = {nullptr, nullptr};
     char* snap = nullptr;
     Item3* items_d = nullptr;
@@ -533,10 +533,11 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     c->L = L;
     c->stream = (hipStream_t)hip_stream;
     c->runs = std::move(runs);
-    // The interpolated-wall step holds more live values per node; the
-    // 32 x 8 tile (two waves per SIMD, 256 registers) keeps them in registers.
-    if (geom->wall_interp)
-        c->tile = 2;
+    // Default tiles, measured on the 512 x 128 x 128 tube: 16 x 12 (four-wave
+    // workgroups, two or three per CU); the interpolated-wall step holds more
+    // live values per node and spills in the 612-thread tiles, and with 16-bit
+    // storage it runs best at 32 x 8.
+    c->tile = (geom->wall_interp && fmt != LBM_STORE_F32) ? 2 : 3;
     c->P = make_inst(*geom, fmt);
     fill_fluid(c->P, *fluid);
     char* ws = (char*)device_workspace;

@@ -91,7 +91,7 @@ def test_tiling_does_not_change_results(gpu_available):
     gives bit-identical populations."""
     cfg = synth.config_tube(lam=32, r0=9.0, a=3.0, theta=120.0, g=1e-4, wall_interp=True)
     ref = None
-    for bx, by, strip in [(32, 16, 16), (64, 8, 4), (32, 8, 7), (32, 16, 100)]:
+    for bx, by, strip in [(32, 16, 16), (64, 8, 4), (32, 8, 7), (16, 12, 9), (32, 16, 100)]:
         sim = _sim(cfg)
         sim.set_tiling(bx, by, strip)
         sim.step(30)
