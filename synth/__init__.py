@@ -389,7 +389,8 @@ def rho03_of(cfg, mask=None):
                pd(z, ini["cz"], nz) ** 2) < ini["r"] ** 2
     elif ini["kind"] == "slug":
         width = ini.get("width", 0.0)
-        phi = slug_fraction(nx, ini["x0"], ini["length"], ini.get("slugs"), width)
+        phi = slug_fraction(nx, ini.get("x0", 0.0), ini.get("length", 0.0), ini.get("slugs"),
+                            width)
         phi = phi[None, None, :] * np.ones(mask.shape)
         if width <= 0:
             oil = phi > 0
