@@ -121,10 +121,9 @@ def test_flat_interface_equal_bulk_pressures():
     assert abs(flipped(ro) / flipped(rw) - 1) > 1e-4
 
 
-@pytest.mark.slow
-def test_laplace_law():
-    """Eq. 11: the pressure jump across a static droplet is linear in 1/R
-    through the origin (Sec. 3.1)."""
+def _laplace_sigma_64():
+    """Laplace-law surface tension (Eq. 11, 2-D: dp = sigma / R) of droplets
+    R = 8..17 on a periodic 64^2 lattice after 4000 steps."""
     n = 64
     inv_r, dps = [], []
     for r0 in (8.0, 11.0, 14.0, 17.0):
@@ -135,15 +134,58 @@ def test_laplace_law():
         L.step(4000)
         m = L.moments()
         c = n // 2
-        rho_hi = m["rho"][0][c, c]
-        rho_lo = m["rho"][0][0, 0]
-        R = analysis.droplet_radius_from_mass(m["rho"][0], rho_hi, rho_lo)
+        R = analysis.droplet_radius_from_mass(m["rho"][0], m["rho"][0][c, c],
+                                              m["rho"][0][0, 0])
         inv_r.append(1.0 / R)
         dps.append(m["p"][c, c] - m["p"][0, 0])
-    sigma, b, r2 = analysis.laplace_fit(inv_r, dps)
+    return analysis.laplace_fit(inv_r, dps)
+
+
+@pytest.mark.slow
+def test_laplace_law():
+    """Eq. 11: the pressure jump across a static droplet is linear in 1/R
+    through the origin (Sec. 3.1)."""
+    sigma, b, r2 = _laplace_sigma_64()
     assert r2 > 0.999
     assert sigma > 0
-    assert abs(b) < 0.05 * sigma * max(inv_r)
+    assert abs(b) < 0.05 * sigma / 8.0
+
+
+@pytest.mark.slow
+def test_flat_interface_mechanical_surface_tension_equals_laplace():
+    """The surface tension of the model two ways: mechanically, as the
+    integral of the normal minus the tangential pressure across a flat
+    interface at rest, and from the Laplace law of droplets.  The pressure
+    tensor is the populations' kinetic flux sum_i f_i c_i c_i plus the
+    interaction part of the species force of Eq. 8, F^a(x) = G rho^a(x)
+    sum_i w_i rho^b(x + c_i) c_i, written as the momentum carried across a
+    plane by the node pairs (x, x + c_i):
+        P^int_ab(x) = -(G / 2) sum_i w_i [rho^o(x) rho^w(x + c_i)
+                                           + rho^w(x) rho^o(x + c_i)] c_ia c_ib,
+    which reduces to the bulk interaction pressure -G T0 rho^o rho^w for
+    uniform densities.  A wrong factor in the force, in the equation of state
+    or in the reported pressure separates the two beyond the 5 % bound."""
+    cx, cy, w, _ = orc.lattice()
+    G = synth.G_DEFAULT
+    nx, ny = 4, 64
+    mask = synth.box_mask(nx, ny)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    oil = (y >= 16) & (y < 48)
+    rho0 = np.stack([np.where(oil, 1.0, 0.03), np.where(oil, 0.03, 1.0)])
+    L = orc.Lattice(orc.Params(nx, ny, tau=(1.0, 1.0), G=G, periodic_y=True), mask, rho0)
+    L.step(8000)
+    ro, rw = L.moments()["rho"]
+    pn = np.zeros((ny, nx))   # P_yy - P_xx
+    for i in range(9):
+        ros = np.roll(ro, (-cy[i], -cx[i]), axis=(0, 1))   # rho^o(x + c_i)
+        rws = np.roll(rw, (-cy[i], -cx[i]), axis=(0, 1))
+        pn += -(G / 2.0) * w[i] * (ro * rws + rw * ros) * (cy[i] ** 2 - cx[i] ** 2)
+        pn += (L.f[0, i] + L.f[1, i]) * (cy[i] ** 2 - cx[i] ** 2)
+    sigma_mech = 0.5 * pn[:, 0].sum()          # two interfaces in the periodic band
+    sigma_lap, b, r2 = _laplace_sigma_64()
+    print("sigma: mechanical %.5f, Laplace %.5f (r2 %.6f)" % (sigma_mech, sigma_lap, r2))
+    assert r2 > 0.999
+    assert abs(sigma_mech / sigma_lap - 1) < 0.05
 
 
 @pytest.mark.slow
