@@ -38,9 +38,10 @@ def test_ramp_matches_oracle_and_brackets_the_bisection(gpu_available):
     ref = odrv.ramp(odrv.OracleEngine([L], equil), [plain], dg, 10000, **rules)[0]
     print("bisection", bis, "ramp gpu", gpu, "oracle", ref)
     assert gpu["flags"] == 0 and ref["flags"] == 0
-    # same level, unless the threshold sits within rounding of a level
-    assert abs(round((gpu["g_crit"] - ref["g_crit"]) / dg)) <= 1
-    assert gpu["g_crit"] == pytest.approx(ref["g_crit"], rel=0.11)
+    # both ramps stop at the same level after the same number of levels
+    assert round((gpu["g_crit"] - lo) / dg) == round((ref["g_crit"] - lo) / dg)
+    assert gpu["g_crit"] == pytest.approx(ref["g_crit"], rel=1e-12)
+    assert gpu["probes"] == ref["probes"]
     # a ramp that lingers 10000 steps per level mobilises at or above the
     # threshold of probes from rest, within one level and the protocols'
     # different histories
