@@ -131,8 +131,6 @@ typedef enum {
                              water elsewhere; the other species rho_lo.  With
                              n_slugs >= 1: oil in every slug (x0_k, length_k) of
                              `slugs` (several slugs in series) */
-    LBM_INIT_FIELD = 4    /* explicit host field rho0 [2][ny][nx]: reserved, currently
-                             rejected with LBM_ERR_UNSUPPORTED */
 } lbm_init_kind;
 
 typedef struct {
@@ -144,7 +142,6 @@ typedef struct {
     double rho_hi, rho_lo;
     double cx, cy, r;    /* DROPLET */
     double x0, length;   /* SLUG */
-    const double* rho0;  /* FIELD (reserved), [2][ny][nx] */
     const double* slugs; /* SLUG with n_slugs >= 1: host [n_slugs][2] pairs
                             (x0, length), length >= 0, read during lbm_init;
                             LBM_ERR_INVALID if null or out of range */

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "LBM_OK", 1: "LBM_ERR_INVALID", 2: "LBM_ERR_DEVICE", 3: "LBM_
                 4: "LBM_ERR_UNSTABLE", 5: "LBM_ERR_BUDGET", 6: "LBM_ERR_UNSUPPORTED"}
 
 GEOM_BOX, GEOM_CHANNEL, GEOM_MASK = 0, 1, 2
-INIT_UNIFORM, INIT_DROPLET, INIT_LAYERS, INIT_SLUG, INIT_FIELD = 0, 1, 2, 3, 4
+INIT_UNIFORM, INIT_DROPLET, INIT_LAYERS, INIT_SLUG = 0, 1, 2, 3
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 
 # Every symbol include/lbm.h declares.
@@ -69,7 +69,6 @@ class LbmInitFields(ctypes.Structure):
                 ("rho_hi", ctypes.c_double), ("rho_lo", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("r", ctypes.c_double),
                 ("x0", ctypes.c_double), ("length", ctypes.c_double),
-                ("rho0", ctypes.POINTER(ctypes.c_double)),
                 ("slugs", ctypes.POINTER(ctypes.c_double)), ("width", ctypes.c_double)]
 
 

@@ -10,14 +10,14 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CP_ADVANCE, CP_BEGIN, CP_MONITORS, CP_RAMP, CP_SET_FORCING, GEOM_BOX, GEOM_CHANNEL, GEOM_MASK,
-                   INIT_DROPLET, INIT_FIELD, INIT_LAYERS, INIT_SLUG, INIT_UNIFORM, OPT_SNAPSHOT,
+                   INIT_DROPLET, INIT_LAYERS, INIT_SLUG, INIT_UNIFORM, OPT_SNAPSHOT,
                    STORE_BF16, STORE_F16, STORE_F32, LbmCpEngine, LbmCpOptions, LbmCpProblem,
                    LbmCpResult, LbmFluid, LbmGeom, LbmInitFields, LbmMonitor, LbmTuneReport,
                    check)
 
 _GEOM_KINDS = {"box": GEOM_BOX, "channel": GEOM_CHANNEL, "mask": GEOM_MASK}
 _INIT_KINDS = {"uniform": INIT_UNIFORM, "droplet": INIT_DROPLET, "layers": INIT_LAYERS,
-               "slug": INIT_SLUG, "field": INIT_FIELD}
+               "slug": INIT_SLUG}
 _STORAGE = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
 
@@ -54,8 +54,7 @@ def fluid_struct(tau, G, rho_s=(0.0, 0.0), g=(0.0, 0.0), reg_order=2):
 
 
 def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=0,
-                core_species=0, x0=0.0, length=0.0, rho0=None, slugs=None, width=0.0,
-                _keep=None):
+                core_species=0, x0=0.0, length=0.0, slugs=None, width=0.0, _keep=None):
     """slugs: optional list of (x0, length) pairs (several slugs in series);
     width: tanh width of the slug interfaces (0: a step)."""
     s = LbmInitFields()
@@ -65,11 +64,6 @@ def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=
     s.wall_rows, s.core_species = int(wall_rows), int(core_species)
     s.x0, s.length = float(x0), float(length)
     s.width = float(width)
-    if rho0 is not None:
-        a = np.ascontiguousarray(rho0, dtype=np.float64)
-        if _keep is not None:
-            _keep.append(a)
-        s.rho0 = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if slugs is not None:
         a = np.ascontiguousarray(slugs, dtype=np.float64).reshape(-1, 2)
         s.n_slugs = a.shape[0]
@@ -80,21 +74,17 @@ def init_struct(kind, rho_hi=1.0, rho_lo=0.03, cx=0.0, cy=0.0, r=0.0, wall_rows=
     return s
 
 
-def structs_from_config(cfg, rho0=None, keep=None):
-    """(geom, fluid, init) structs from a workload dict; rho0 forces an
-    explicit initial field."""
+def structs_from_config(cfg, keep=None):
+    """(geom, fluid, init) structs from a workload dict."""
     geom = geom_struct(cfg["kind"], cfg["nx"], cfg["ny"], cfg.get("lam", 0.0),
                        cfg.get("h0", 0.0), cfg.get("a", 0.0), cfg.get("mask"), keep,
                        cfg.get("wall_interp", 0), cfg.get("y_offset", 0.0),
                        cfg.get("island", (0.0, 0.0)))
     fluid = fluid_struct(cfg["tau"], cfg["G"], cfg.get("rho_s", (0, 0)), cfg.get("g", (0, 0)),
                          cfg.get("reg_order", 2))
-    if rho0 is not None:
-        init = init_struct("field", rho0=rho0, _keep=keep)
-    else:
-        ini = dict(cfg["init"])
-        kind = ini.pop("kind")
-        init = init_struct(kind, _keep=keep, **ini)
+    ini = dict(cfg["init"])
+    kind = ini.pop("kind")
+    init = init_struct(kind, _keep=keep, **ini)
     return geom, fluid, init
 
 
@@ -247,7 +237,7 @@ def cp_problem(cfg, g_lo, g_hi, sigma, rho_bar, equil_steps, max_steps, keep=Non
     """Critical-pressure problem from a channel workload dict (min_steps 0:
     the options' value)."""
     keep = [] if keep is None else keep  # host arrays the structs point to
-    g, f, i = structs_from_config(cfg, None, keep)
+    g, f, i = structs_from_config(cfg, keep)
     p = LbmCpProblem()
     p.geom, p.fluid, p.init = g, f, i
     p._keep = keep
@@ -354,11 +344,9 @@ class Simulation:
     """A context plus the torch device workspace that backs it.
 
     configs: list of workload dicts (keys nx, ny, kind, lam, h0, a, tau, G,
-    rho_s, g, init); fields: optional list (same length) of explicit initial
-    density arrays [2, ny, nx] (None entries use the config's preset)."""
+    rho_s, g, init; the initial state is the config's preset)."""
 
-    def __init__(self, configs, fields=None, storage="f32", device="cuda", snapshot=False,
-                 stream=None):
+    def __init__(self, configs, storage="f32", device="cuda", snapshot=False, stream=None):
         import torch  # device memory and streams only
 
         _lib.load()
@@ -366,8 +354,7 @@ class Simulation:
         keep = []
         geoms, fluids, inits = [], [], []
         for k, cfg in enumerate(self.configs):
-            rho0 = None if fields is None else fields[k]
-            g, f, i = structs_from_config(cfg, rho0, keep)
+            g, f, i = structs_from_config(cfg, keep)
             geoms.append(g)
             fluids.append(f)
             inits.append(i)

@@ -536,14 +536,9 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
         if (st != LBM_OK)
             return st;
         const lbm_init_fields& in = inits[k];
-        if (in.kind < LBM_INIT_UNIFORM || in.kind > LBM_INIT_FIELD)
+        if (in.kind < LBM_INIT_UNIFORM || in.kind > LBM_INIT_SLUG)
             return fail(LBM_ERR_INVALID, "instance %d: unknown init kind %d", k, in.kind);
-        if (in.kind == LBM_INIT_FIELD)
-            return fail(LBM_ERR_UNSUPPORTED,
-                        "instance %d: explicit initial fields (LBM_INIT_FIELD) are switched "
-                        "off in this version of the library; use a preset", k);
-        if (in.kind != LBM_INIT_FIELD &&
-            (!(in.rho_hi > 0.0) || !(in.rho_lo > 0.0) || !std::isfinite(in.rho_hi + in.rho_lo)))
+        if (!(in.rho_hi > 0.0) || !(in.rho_lo > 0.0) || !std::isfinite(in.rho_hi + in.rho_lo))
             return fail(LBM_ERR_INVALID, "instance %d: rho_hi, rho_lo must be > 0", k);
         if (in.kind == LBM_INIT_LAYERS && (in.core_species < 0 || in.core_species > 1))
             return fail(LBM_ERR_INVALID, "instance %d: core_species must be 0 or 1", k);

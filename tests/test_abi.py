@@ -78,8 +78,8 @@ def test_init_rejects_bad_fluid_and_init_on_host():
         _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7, g=(0.5, 0))], ok_init)
     assert "g[0]" in str(e.value)
     with pytest.raises(_lib.LbmError) as e:
-        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct("field")])
-    assert e.value.status == 6 and "switched off" in str(e.value)
+        _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], [binding.init_struct(4)])
+    assert e.value.status == 1 and "unknown init kind" in str(e.value)
     with pytest.raises(_lib.LbmError) as e:
         _try_init(g, [binding.fluid_struct((1.0, 1.0), -2.7)], ok_init, ws_bytes=1024)
     assert e.value.status == 3

@@ -9,9 +9,9 @@ from tests.gpu_util import (assert_monitors_match, field_rel_err, fp32_storage_f
 pytestmark = pytest.mark.gpu
 
 
-def _sim(cfgs, fields=None):
+def _sim(cfgs):
     from paper_1601_00918_amd import Simulation
-    return Simulation(cfgs, fields=fields)
+    return Simulation(cfgs)
 
 
 @pytest.mark.parametrize("which", ["droplet", "poiseuille", "channel"])
