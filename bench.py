@@ -347,7 +347,9 @@ def solves_per_hour(args):
     from paper_1601_00918_amd import surrogate as sg
 
     SIG, RHO = 0.161, 1.03
-    rules = dict(rel_tol=0.005, chunk_steps=500, still_chunks=3)
+    # verbose: the driver prints a line per classified probe (progress of the
+    # long phases)
+    rules = dict(rel_tol=0.005, chunk_steps=500, still_chunks=3, verbose=1)
     lams = tuple(int(v) for v in args.lams.split(","))
     n_eval = args.solves
     train = synth.config_cp_set(args.train_solves or n_eval, seed=1611, lams=lams)

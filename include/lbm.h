@@ -380,7 +380,9 @@ typedef struct {
                                the equilibration when every problem's equil_steps covers
                                its steps; default 0 */
     int32_t protocol;       /* LBM_CP_BISECT (default) or LBM_CP_RAMP */
-    int32_t reserved;
+    int32_t verbose;        /* 1: one line on stderr per classified probe or ramp level
+                               (problem index, probe count, forcing, outcome, steps);
+                               default 0 */
     double ramp_dg;         /* LBM_CP_RAMP: forcing increment per level (> 0) */
     int64_t ramp_steps;     /* LBM_CP_RAMP: steps per level, a multiple of chunk_steps
                                (default 40000) */

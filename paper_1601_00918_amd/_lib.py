@@ -93,7 +93,7 @@ class LbmCpOptions(ctypes.Structure):
                 ("max_probes", ctypes.c_int32), ("verify_bracket", ctypes.c_int32),
                 ("min_steps", ctypes.c_int64), ("storage", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("protocol", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ramp_dg", ctypes.c_double),
+                ("verbose", ctypes.c_int32), ("ramp_dg", ctypes.c_double),
                 ("ramp_steps", ctypes.c_int64)]
 
 

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -98,7 +99,7 @@ lbm_status check_options(const lbm_cp_options& o)
         !(o.still_frac > 0.0) || o.chunk_steps < 2 || (o.chunk_steps & 1) || o.still_chunks < 1 ||
         o.max_probes < 1 || o.min_steps < 0 || o.verify_bracket < 0 || o.verify_bracket > 2 ||
         o.storage < LBM_STORE_F32 ||
-        o.storage > LBM_STORE_BF16)
+        o.storage > LBM_STORE_BF16 || o.verbose < 0 || o.verbose > 1)
         return fail(LBM_ERR_INVALID, "invalid critical-pressure options");
     if (o.protocol != LBM_CP_BISECT && o.protocol != LBM_CP_RAMP)
         return fail(LBM_ERR_INVALID, "unknown critical-pressure protocol %d", o.protocol);
@@ -198,6 +199,10 @@ lbm_status cp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm_c
                 continue;
             ++r.probes;
             const bool moving = out == kMoving;
+            if (o.verbose)
+                std::fprintf(stderr, "lbm_cp: problem %d probe %d g %.6e %s after %lld steps\n",
+                             k, r.probes, s.g, moving ? "moving" : "static",
+                             (long long)s.probe_steps);
             switch (s.phase) {
             case kVerifyLo:
                 if (moving && s.widen < kMaxWiden) {
@@ -368,6 +373,9 @@ lbm_status ramp_run(CpEngine& eng, const lbm_cp_problem* probs, int n, const lbm
                 } else {
                     ++s.level;
                     ++r.probes;
+                    if (o.verbose)
+                        std::fprintf(stderr, "lbm_cp: problem %d ramp level %d g %.6e\n", k,
+                                     s.level, g_next);
                     s.g = g_next;
                     s.level_steps = 0;
                     if ((e = eng.set_forcing(k, s.g)) != LBM_OK)

@@ -243,6 +243,12 @@ def test_lbm3d_critical_pressure_validates_on_the_host():
         st = lib.lbm3d_critical_pressure(arr, 1, ctypes.byref(opts), ctypes.c_void_p(1 << 20),
                                          1 << 30, None, res)
         assert st == 1 and what in lib.lbm_last_error().decode()
+    # options are checked first: verbose is 0 or 1
+    bad = binding.cp_options(verbose=2)
+    arr = (_lib.Lbm3dCpProblem * 1)(box)
+    st = lib.lbm3d_critical_pressure(arr, 1, ctypes.byref(bad), ctypes.c_void_p(1 << 20),
+                                     1 << 30, None, res)
+    assert st == 1 and "options" in lib.lbm_last_error().decode()
 
 
 def test_interpolated_walls_validate_on_the_host():
