@@ -34,7 +34,7 @@ _long = pytest.mark.skipif(os.environ.get("LBM_STUDIES") != "1",
                            reason="long study; set LBM_STUDIES=1 to run it")
 
 
-@pytest.mark.parametrize("lam", [128, pytest.param(256, marks=_long),
+@pytest.mark.parametrize("lam", [128, 256,
                                  pytest.param(512, marks=_long)])
 def test_channel_critical_pressure_vs_planar_young_laplace(gpu_available, lam):
     """Bisection to 1 %.  A water-wet slug forced below its threshold first

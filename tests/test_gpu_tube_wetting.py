@@ -79,7 +79,6 @@ def test_tube_contact_angle_and_its_spread_over_axis_offsets(gpu_available):
     _angle_study(8.0)
 
 
-@studies
 @pytest.mark.parametrize("radius", [6.0, 12.0])
 def test_tube_contact_angle_at_other_resolutions(gpu_available, radius):
     """The same study in tubes of radius 6 and 12 (the paper's other neck
