@@ -61,7 +61,7 @@ def test_few_steps_and_1000_steps_match_oracle(gpu_available, which):
     # Velocity: the plates' u is the contact lines' spurious current (max|u|
     # ~0.02), which the wall blends' FP32 arithmetic perturbs by 8-9 x the
     # storage floor (rho: 7.3e-6 against a floor of 8.7e-7 at offset 0.2);
-    # held to 1e-4, the benchmark spec's 1e-5 is not met on these cases.
+    # held to 1e-4: the 1e-5 moment bar is not met on these cases.
     u_bound = max(velocity_bound(floor_u), WALL_U_BOUND)
     assert max(eu) <= u_bound
     assert_monitors_match(ref["mon"], got["mon"], u_bound, cfg["G"])
