@@ -278,3 +278,29 @@ def test_non_finite_states_are_flagged_not_refused():
             return out
     r = binding.lbm_cp_drive(Broken(plain, [1e-5]), probs, binding.cp_options())[0]
     assert r["flags"] & binding._lib.CP_UNSTABLE
+
+
+def test_verbose_logs_every_classified_probe(capfd):
+    """verbose = 1: one stderr line per classified probe (bisection) or ramp
+    level, naming the problem, the probe count and the forcing; nothing
+    without it."""
+    g_stars = [3.3e-5, 1.1e-6]
+    probs, plain = _problems(g_stars)
+    res = binding.lbm_cp_drive(FakeEngine(plain, g_stars), probs, binding.cp_options())
+    assert "lbm_cp:" not in capfd.readouterr().err
+    res_v = binding.lbm_cp_drive(FakeEngine(plain, g_stars), probs,
+                                 binding.cp_options(verbose=1))
+    lines = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("lbm_cp:")]
+    assert [r["g_crit"] for r in res_v] == [r["g_crit"] for r in res]
+    assert len(lines) == sum(r["probes"] for r in res_v)
+    for k, r in enumerate(res_v):
+        mine = [ln for ln in lines if ln.startswith("lbm_cp: problem %d probe" % k)]
+        assert len(mine) == r["probes"]
+        assert mine[-1].startswith("lbm_cp: problem %d probe %d g " % (k, r["probes"]))
+        assert all(("moving" in ln) != ("static" in ln) for ln in mine)
+    rp, rplain = _ramp_problems(g_stars[:1])
+    opts = binding.cp_options(protocol="ramp", ramp_dg=0.04 * g_stars[0], ramp_steps=40000,
+                              chunk_steps=1000, verbose=1)
+    r = binding.lbm_cp_drive(RampEngine(rplain, g_stars[:1]), rp, opts)[0]
+    levels = [ln for ln in capfd.readouterr().err.splitlines() if "ramp level" in ln]
+    assert len(levels) == r["probes"] - 1   # the first level is not a step up
