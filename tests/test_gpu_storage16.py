@@ -148,3 +148,46 @@ def test_snapshot_restore_is_exact(gpu_available):
     sim.snapshot_restore(-1)
     for k in range(2):
         assert np.array_equal(sim.populations(k), saved[k])
+
+
+# Storage floors after 1000 steps of the extended kernels' workloads (rho, u, p;
+# tests/storage_floor.py's floor() on these configs): third-order
+# regularization on the lambda = 64 channel, and the bypass channel with its
+# solid island (two fluid runs per column in the island's columns).
+EXT_FLOOR = {
+    "f16": {"channel-reg3": (1.16e-4, 4.49e-3, 9.64e-5), "island64": (2.05e-4, 3.31e-3, 1.30e-4)},
+    "bf16": {"channel-reg3": (1.77e-3, 6.25e-2, 8.03e-4), "island64": (1.39e-3, 5.27e-2, 8.64e-4)},
+}
+
+
+def _ext_cfg(which):
+    if which == "channel-reg3":
+        return dict(synth.config_channel(lam=64, theta=120.0, g=1e-5, tau=(0.7, 1.3)),
+                    reg_order=3)
+    return synth.config_bypass(lam=64, theta=120.0, g=1e-5, tau=(0.8, 1.2))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("which", ["channel-reg3", "island64"])
+def test_extended_kernels_in_16bit_storage_track_the_oracle(gpu_available, which, storage):
+    """The extended step instances (third-order regularization, two-run
+    columns) in the 16-bit formats against the FP64 oracle after 1000 steps:
+    every field within four times its storage floor, mass as in the plain
+    kernels."""
+    cfg = _ext_cfg(which)
+    L, mask, rho0 = oracle_lattice(cfg)
+    sim = _sim([cfg], storage)
+    m0 = sim.monitors()[0]["mass"]
+    sim.step(1000)
+    L.step(1000)
+    ref, got = L.moments(), sim.moments(0)
+    erho = max(field_rel_err(ref["rho"], got["rho"], mask))
+    eu = max(field_rel_err(ref["u"], got["u"], mask))
+    ep = max(field_rel_err(ref["p"][None], got["p"][None], mask))
+    m1 = sim.monitors()[0]["mass"]
+    drift = [abs(m1[k] / m0[k] - 1) for k in range(2)]
+    fr, fu, fp = EXT_FLOOR[storage][which]
+    print(which, storage, "rho %.2e (floor %.1e)  u %.2e (floor %.1e)  p %.2e (floor %.1e)  "
+          "mass drift %.1e %.1e" % (erho, fr, eu, fu, ep, fp, drift[0], drift[1]), flush=True)
+    assert erho <= 4 * fr and eu <= 4 * fu and ep <= 4 * fp
+    assert max(drift) <= (1e-5 if storage == "f16" else 5e-5)
