@@ -191,3 +191,40 @@ def test_extended_kernels_in_16bit_storage_track_the_oracle(gpu_available, which
           "mass drift %.1e %.1e" % (erho, fr, eu, fu, ep, fp, drift[0], drift[1]), flush=True)
     assert erho <= 4 * fr and eu <= 4 * fu and ep <= 4 * fp
     assert max(drift) <= (1e-5 if storage == "f16" else 5e-5)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_slug_list_with_tanh_interfaces_starts_at_the_oracle_state(gpu_available, lattice,
+                                                                   storage):
+    """Two slugs with tanh interfaces of width 2 in 16-bit storage: every
+    initial population equals the oracle's rest equilibrium from the same
+    synthetic field within one rounding of the stored deviation
+    rho0(reader) - R(x) (half a unit in its last place, at most one unit of
+    max rho0), times the weight."""
+    ulp = 2.0 ** -11 if storage == "f16" else 2.0 ** -8
+    slugs = [(6, 40), (100, 30)]
+    if lattice == "d2q9":
+        cfg = synth.config_channel(lam=64, theta=90.0)
+        cfg["init"] = dict(kind="slug", slugs=slugs, width=2.0)
+        L, mask, _ = oracle_lattice(cfg)
+        f = _sim([cfg], storage).populations(0)
+        w = W[None, :, None, None]
+        ref = L.f
+    else:
+        from oracle import lbm3d as o3
+        from paper_1601_00918_amd.binding3d import Simulation3D
+        from tests.test_gpu_d3q19 import _to_oracle_order
+        cfg = synth.config_tube(lam=48, r0=10.0, a=4.0, nx=144, theta=90.0)
+        cfg["init"] = dict(kind="slug", slugs=slugs, width=2.0)
+        mask = synth.mask3_of(cfg)
+        L = o3.Lattice3(o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                                   rho_s=cfg["rho_s"], g=cfg["g"]), mask,
+                        synth.rho03_of(cfg, mask))
+        f = _to_oracle_order(Simulation3D(cfg, storage=storage).populations())
+        w = o3.lattice()[3][None, :, None, None, None]
+        ref = L.f
+    e = (np.abs(f - ref) / w).max()
+    bound = ulp * max(synth.RHO_HI, 1.0) + 1e-6
+    print(lattice, storage, "max |df| / w = %.3e (bound %.3e)" % (e, bound), flush=True)
+    assert e <= bound
