@@ -70,7 +70,7 @@ typedef enum {
 typedef struct {
     int32_t kind;          /* lbm_geom_kind */
     int32_t nx, ny;        /* bounding box in nodes; 1 <= nx, ny <= 32768 */
-    int32_t wall_interp;   /* LBM_GEOM_CHANNEL, FP32 storage: 1 places the walls at
+    int32_t wall_interp;   /* LBM_GEOM_CHANNEL, any storage: 1 places the walls at
                               their sub-lattice positions by linear interpolated
                               bounce-back (Bouzidi, Firdaouss and Lallemand 2001):
                               a population leaving a fluid node towards a wall met

@@ -128,7 +128,7 @@ __device__ __forceinline__ float rho9(const float* f)
     return ((f[0] + a13) + a24) + (a57 + a68);
 }
 
-// Interpolated walls (FP32 storage, instances with a wall table): the wall
+// Interpolated walls (instances with a wall table, any storage): the wall
 // fraction q of the link from node (x, y) along -c_j comes from the table the
 // runtime computes in FP64 (a wall exactly half-way gives q = 1/2, and the
 // blend below is then the half-way value itself); the linear interpolated
@@ -140,6 +140,8 @@ __device__ __forceinline__ float rho9(const float* f)
 // is taken from the node's rest population, so each species keeps its mass.
 // Owner and halo lanes use these same functions and the same summation order,
 // so a wall node's density is bitwise the same whichever workgroup computes it.
+// In the 16-bit formats the blend works on decoded values: the partner is
+// decoded with its own node's reference density.
 __device__ __forceinline__ float ibb_q(const InstDev& P, int x, int y, const Col& c, int j)
 {
     return P.wq[(x * kWallSlots + wall_slot(y, c.lo, c.hi)) * 8 + (j - 1)];
@@ -453,7 +455,37 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 S::unpack(rawp[i], raw[i], raw[9 + i]);
-            if constexpr (EXT && !S::kRef && !PY) {
+            // Reference densities (16-bit formats) of the nodes around this one:
+            // rrow[1 - c_y][c_x] is node (x + c_x, r + c_y), from one of three
+            // ring rows.
+            const float2* rrow[3] = {rref + ((r + 1) & 3) * RW + tid + 2,   // row r + 1
+                                     rref + (r & 3) * RW + tid + 2,         // row r
+                                     rref + ((r - 1) & 3) * RW + tid + 2};  // row r - 1
+            if (S::kRef) {
+                // Reference density of each pull's source node (x - c_i, r -
+                // c_y,i): a constant offset from this column in one of three
+                // ring rows; the node's own after bounce-back.
+                const uint32_t bbm = bb_next;
+                const float2 Rown = rrow[1][0];
+                if (__ballot(bbm != 0u) == 0) {  // no bounce-back in the wave
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
+                        raw[i] = kW36[i] * (Rs.x + raw[i]);
+                        raw[9 + i] = kW36[i] * (Rs.y + raw[9 + i]);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
+                        const bool bb = (bbm >> i) & 1u;
+                        const float Ro = bb ? Rown.x : Rs.x, Rw = bb ? Rown.y : Rs.y;
+                        raw[i] = kW36[i] * (Ro + raw[i]);
+                        raw[9 + i] = kW36[i] * (Rw + raw[9 + i]);
+                    }
+                }
+            }
+            if constexpr (EXT && !PY) {
                 if (P.wq && bb_next) {
                     float dmo = 0.0f, dmw = 0.0f;  // added beyond half-way bounce-back
 #pragma unroll
@@ -475,8 +507,14 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                             o_extra = PB * ((uint32_t)(i * P.pitch) + (uint32_t)(rr * RS + x));
                         }
                         float eo = raw[i], ew = raw[9 + i];
-                        if (use)
+                        if (use) {
                             S::unpack(S::load(base + o_extra), eo, ew);
+                            if constexpr (S::kRef) {  // x + c_i, or the node itself
+                                const float2 Re = q < 0.5f ? rrow[1 - cy][cx] : rrow[1][0];
+                                eo = kW36[i] * (Re.x + eo);
+                                ew = kW36[i] * (Re.y + ew);
+                            }
+                        }
                         const float bo = ibb_blend(q, raw[i], eo);
                         const float bw = ibb_blend(q, raw[9 + i], ew);
                         dmo += bo - raw[i];
@@ -486,33 +524,6 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                     }
                     raw[0] -= dmo;
                     raw[9] -= dmw;
-                }
-            }
-            if (S::kRef) {
-                // Reference density of each pull's source node (x - c_i, r -
-                // c_y,i): a constant offset from this column in one of three
-                // ring rows; the node's own after bounce-back.
-                const uint32_t bbm = bb_next;
-                const float2* rrow[3] = {rref + ((r + 1) & 3) * RW + tid + 2,   // c_y = -1
-                                         rref + (r & 3) * RW + tid + 2,         // c_y = 0
-                                         rref + ((r - 1) & 3) * RW + tid + 2};  // c_y = +1
-                const float2 Rown = rrow[1][0];
-                if (__ballot(bbm != 0u) == 0) {  // no bounce-back in the wave
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
-                        raw[i] = kW36[i] * (Rs.x + raw[i]);
-                        raw[9 + i] = kW36[i] * (Rs.y + raw[9 + i]);
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
-                        const bool bb = (bbm >> i) & 1u;
-                        const float Ro = bb ? Rown.x : Rs.x, Rw = bb ? Rown.y : Rs.y;
-                        raw[i] = kW36[i] * (Ro + raw[i]);
-                        raw[9 + i] = kW36[i] * (Rw + raw[9 + i]);
-                    }
                 }
             }
             cur[0] = moments9(raw);
@@ -533,7 +544,16 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
             float e0 = 0.0f, e1 = 0.0f;  // interpolated walls: added beyond half-way
             if (hlane && hfl) {
                 S::unpack(hrawp, v0, v1);
-                if constexpr (EXT && !S::kRef && !PY) {
+                if (S::kRef) {
+                    const int ch = hside ? wdt + 2 : 1;
+                    const int sl = hbb_next ? (r & 3) : ((r - hcy) & 3);
+                    const int cl = hbb_next ? ch : ch - hcx;
+                    const float2 R = rref[sl * RW + cl];
+                    const float w = dir_w36(hd);
+                    v0 = w * (R.x + v0);
+                    v1 = w * (R.y + v1);
+                }
+                if constexpr (EXT && !PY) {
                     if (P.wq && hbb_next) {
                         const float q = ibb_q(P, hx, rr, hgc, hd);
                         uint32_t o_extra;
@@ -548,8 +568,18 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                             o_extra = PB * ((uint32_t)(hd * P.pitch) + (uint32_t)(rr * RS + hx));
                         }
                         float eo = v0, ew = v1;
-                        if (use)
+                        if (use) {
                             S::unpack(S::load(base + o_extra), eo, ew);
+                            if constexpr (S::kRef) {  // x + c_j, or the node itself
+                                const int ch = hside ? wdt + 2 : 1;
+                                const int sl = q < 0.5f ? ((r + hcy) & 3) : (r & 3);
+                                const int cl = q < 0.5f ? ch + hcx : ch;
+                                const float2 Re = rref[sl * RW + cl];
+                                const float w = dir_w36(hd);
+                                eo = w * (Re.x + eo);
+                                ew = w * (Re.y + ew);
+                            }
+                        }
                         const float b0 = ibb_blend(q, v0, eo);
                         const float b1 = ibb_blend(q, v1, ew);
                         e0 = b0 - v0;
@@ -558,15 +588,6 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                         v1 = b1;
                     }
                 }
-                if (S::kRef) {
-                    const int ch = hside ? wdt + 2 : 1;
-                    const int sl = hbb_next ? (r & 3) : ((r - hcy) & 3);
-                    const int cl = hbb_next ? ch : ch - hcx;
-                    const float2 R = rref[sl * RW + cl];
-                    const float w = dir_w36(hd);
-                    v0 = w * (R.x + v0);
-                    v1 = w * (R.y + v1);
-                }
             }
             float q0[9], q1[9];
 #pragma unroll
@@ -574,7 +595,7 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                 q0[j] = __shfl(v0, (tid & ~15) + j, 64);
                 q1[j] = __shfl(v1, (tid & ~15) + j, 64);
             }
-            if constexpr (EXT && !S::kRef && !PY) {
+            if constexpr (EXT && !PY) {
                 if (P.wq) {
                     float dm0 = 0.0f, dm1 = 0.0f;
 #pragma unroll
@@ -862,39 +883,37 @@ __global__ void init_kernel(void* __restrict__ A, const InstDev* __restrict__ in
         }
         double rho_o = init_density(ini, P, 0, xr, yr);
         double rho_w = init_density(ini, P, 1, xr, yr);
-        if constexpr (!S::kRef) {
-            // Interpolated walls: x reads this slot as the half-way value of
-            // direction j = opp(i); when the wall is at q >= 1/2 the first
-            // pull blends it with slot (x, j), which holds w rho0(x + c_j) for
-            // the node x + c_j that pulls it.  Store the value that makes the
-            // blend w_i rho0(x), the rest state.  (For q < 1/2 the blend
-            // partner already holds w_i rho0(x).)
-            if (P.wq && xr == x && yr == y && i > 0) {
-                const int j = kOpp[i];
+        // Interpolated walls: x reads this slot as the half-way value of
+        // direction j = opp(i); when the wall is at q >= 1/2 the first
+        // pull blends it with slot (x, j), which holds w rho0(x + c_j) for
+        // the node x + c_j that pulls it.  Store the value that makes the
+        // blend w_i rho0(x), the rest state.  (For q < 1/2 the blend
+        // partner already holds w_i rho0(x).)
+        if (P.wq && xr == x && yr == y && i > 0) {
+            const int j = kOpp[i];
+            const float q = ibb_q(P, x, y, cols[P.col_off + x], j);
+            const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j];
+            if (q >= 0.5f && fluid(xo, yo)) {
+                const double two_q = 2.0 * (double)q;
+                rho_o = two_q * rho_o - (two_q - 1.0) * init_density(ini, P, 0, xo, yo);
+                rho_w = two_q * rho_w - (two_q - 1.0) * init_density(ini, P, 1, xo, yo);
+            }
+        }
+        // The first pull takes from the rest population what those
+        // blends add to their half-way slots, (2q - 1) w_j (rho0(x + c_j)
+        // - rho0(x)) per link; store it in advance so that the pulled rest
+        // population is w_0 rho0(x).
+        if (P.wq && i == 0) {
+            const double ro = rho_o, rw = rho_w;
+            for (int j = 1; j < 9; ++j) {
+                if (fluid(wrapi(x - kCx[j], P.nx), y - kCy[j]))
+                    continue;
                 const float q = ibb_q(P, x, y, cols[P.col_off + x], j);
                 const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j];
                 if (q >= 0.5f && fluid(xo, yo)) {
-                    const double two_q = 2.0 * (double)q;
-                    rho_o = two_q * rho_o - (two_q - 1.0) * init_density(ini, P, 0, xo, yo);
-                    rho_w = two_q * rho_w - (two_q - 1.0) * init_density(ini, P, 1, xo, yo);
-                }
-            }
-            // The first pull takes from the rest population what those
-            // blends add to their half-way slots, (2q - 1) w_j (rho0(x + c_j)
-            // - rho0(x)) per link; store it in advance so that the pulled rest
-            // population is w_0 rho0(x).
-            if (P.wq && i == 0) {
-                const double ro = rho_o, rw = rho_w;
-                for (int j = 1; j < 9; ++j) {
-                    if (fluid(wrapi(x - kCx[j], P.nx), y - kCy[j]))
-                        continue;
-                    const float q = ibb_q(P, x, y, cols[P.col_off + x], j);
-                    const int xo = wrapi(x + kCx[j], P.nx), yo = y + kCy[j];
-                    if (q >= 0.5f && fluid(xo, yo)) {
-                        const double c = (2.0 * (double)q - 1.0) * (kW36[j] / kW36[0]);
-                        rho_o += c * (init_density(ini, P, 0, xo, yo) - ro);
-                        rho_w += c * (init_density(ini, P, 1, xo, yo) - rw);
-                    }
+                    const double c = (2.0 * (double)q - 1.0) * (kW36[j] / kW36[0]);
+                    rho_o += c * (init_density(ini, P, 0, xo, yo) - ro);
+                    rho_w += c * (init_density(ini, P, 1, xo, yo) - rw);
                 }
             }
         }

@@ -526,9 +526,6 @@ lbm_status lbm_init(const lbm_geom* geoms, const lbm_fluid* fluids,
     if ((uintptr_t)device_workspace % kAlign)
         return fail(LBM_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
     for (int k = 0; k < n_inst; ++k) {
-        if (geoms[k].wall_interp && (storage & 0xff) != LBM_STORE_F32)
-            return fail(LBM_ERR_UNSUPPORTED,
-                        "instance %d: interpolated walls need FP32 storage", k);
         lbm_status st = check_geom(geoms[k]);
         if (st != LBM_OK)
             return st;

@@ -261,7 +261,6 @@ def test_interpolated_walls_validate_on_the_host():
     assert interp - plain >= 64 * 32 * 4      # the wall table: 32 floats per column
     cases = [
         (binding.geom_struct("box", 32, 32, wall_interp=1), "f32", 6, "analytic channel"),
-        (binding.geom_struct("channel", 64, 18, wall_interp=1, **flat), "f16", 6, "FP32"),
         (binding.geom_struct("channel", 64, 18, wall_interp=2, **flat), "f32", 1, "0 or 1"),
         (binding.geom_struct("channel", 64, 18, y_offset=1.5, **flat), "f32", 1, "y_offset"),
         # slope a 2 pi / lambda = 1.57: fluid runs of neighbouring columns
