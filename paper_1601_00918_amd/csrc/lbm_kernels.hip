@@ -128,6 +128,49 @@ __device__ __forceinline__ float rho9(const float* f)
     return ((f[0] + a13) + a24) + (a57 + a68);
 }
 
+// Scaled population (36 w_i)(R + d) of a 16-bit deviation d with reference
+// density R, w36 = 36 w_i in {1, 4, 16}: one rounding of the exact w36 d +
+// w36 R, which for a power of two equals the rounded sum scaled, written as an
+// FMA so that the conversion of the binary16 d folds into it.  one is 1.0
+// hidden from the compiler (which would otherwise turn the w36 = 1 case into
+// a separate conversion and add).
+__device__ __forceinline__ float dec16(float d, float w36, float R, float one)
+{
+    return w36 == 1.0f ? fmaf(d, one, R) : fmaf(d, w36, w36 * R);
+}
+
+// Halo lanes: within each group of 16 lanes, direction j sits at lane
+// kHaloLane[j] and the other lanes hold zero, so that halo_rho's butterfly
+// adds exactly the pairs rho9 adds, in its order: lanes (0, 1) = (f1, f3),
+// (2, 3) = (f0, 0), (4, 5) = (f2, f4), (8, 9) = (f5, f7), (10, 11) = (f6, f8).
+// Adding a zero is exact, and every lane pair holds equal sums after each
+// level, so all 16 lanes end with rho9's value, bit for bit.
+constexpr int kHaloLane[9] = {2, 0, 4, 1, 5, 8, 10, 9, 11};
+__device__ __forceinline__ int halo_dir(int lane)
+{
+    return lane == 0 ? 1 : lane == 1 ? 3 : lane == 2 ? 0 : lane == 4 ? 2 : lane == 5 ? 4
+         : lane == 8 ? 5 : lane == 9 ? 7 : lane == 10 ? 6 : lane == 11 ? 8 : -1;
+}
+
+// v + the value of the partner lane selected by the DPP control CTRL (lanes
+// of one row of 16).
+template <int CTRL>
+__device__ __forceinline__ float dpp_pair_sum(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+// Density of a halo node from its 16 halo lanes (whole wave active): lane
+// pairs (i, i ^ 1), then (i, i ^ 2) within quads, then mirrored halves of 8
+// and of 16.
+__device__ __forceinline__ float halo_rho(float v)
+{
+    v = dpp_pair_sum<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_pair_sum<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_pair_sum<0x141>(v);  // row_half_mirror
+    return dpp_pair_sum<0x140>(v);  // row_mirror
+}
+
 // Interpolated walls (instances with a wall table, any storage): the wall
 // fraction q of the link from node (x, y) along -c_j comes from the table the
 // runtime computes in FP64 (a wall exactly half-way gives q = 1/2, and the
@@ -336,14 +379,17 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         g.c = cols[P.col_off + x];
         g.p = cols[P.col_off + xp];
     }
-    // Halo lanes of wave 0: lane 16 side + j pulls direction j of the column
-    // left (side 0) or right (side 1) of the workgroup.
+    // Halo lanes of wave 0: lanes 16 side + 0 .. 15 serve the column left
+    // (side 0) or right (side 1) of the workgroup; lane 16 side + kHaloLane[j]
+    // pulls its direction j (the layout lets a four-level butterfly of
+    // lane-pair sums reproduce rho9's summation order, halo_rho).
     const int hj = tid & 15, hside = (tid >> 4) & 1;
     const bool hgrp = tid < 32;
-    const bool hlane = hgrp && hj < 9;
+    const int hdir = halo_dir(hj);
+    const bool hlane = hgrp && hdir >= 0;
     const int hx = hside ? wrapi(it.x0 + wdt, P.nx) : wrapi(it.x0 - 1, P.nx);
     const int hxm = wrapi(hx - 1, P.nx), hxp = wrapi(hx + 1, P.nx);
-    const int hd = hj < 9 ? hj : 0;
+    const int hd = hdir >= 0 ? hdir : 0;
     const int hcx = dir_cx(hd), hcy = dir_cy(hd), hopp = dir_opp(hd);
     const int hsx = hcx == 1 ? hxm : (hcx == -1 ? hxp : hx);
     Col hgc{0, 0, 1, 0}, hgs{0, 0, 1, 0}, hge{0, 0, 1, 0};  // halo column, its source, the one beyond
@@ -353,11 +399,11 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         if (EXT)
             hge = cols[P.col_off + (hcx == 1 ? hxp : (hcx == -1 ? hxm : hx))];
     }
-    // Reference-density lanes of wave 0 (16-bit formats): lanes 16 side + 9
-    // and + 10 load the reference pairs of the two columns beyond each side
+    // Reference-density lanes of wave 0 (16-bit formats): lanes 16 side + 12
+    // and + 13 load the reference pairs of the two columns beyond each side
     // that halo pulls reach (ring columns 0, 1 and wdt + 2, wdt + 3).
-    const bool rlane = S::kRef && hgrp && (hj == 9 || hj == 10);
-    const int rcol = hside ? wdt + 2 + (hj - 9) : hj - 9;
+    const bool rlane = S::kRef && hgrp && (hj == 12 || hj == 13);
+    const int rcol = hside ? wdt + 2 + (hj - 12) : hj - 12;
     const int rx = wrapi(it.x0 - 2 + rcol, P.nx);
 
     const int64_t n_nodes = (int64_t)P.nx * P.ny;
@@ -440,6 +486,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
         lds_barrier();
     }
     const uint32_t seed_h = lowbias32(seed);
+    float one = 1.0f;
+    __asm__("" : "+s"(one));
 
     Mom prev[2], cur[2];
     bool prev_fluid = false;
@@ -471,8 +519,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
 #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
-                        raw[i] = kW36[i] * (Rs.x + raw[i]);
-                        raw[9 + i] = kW36[i] * (Rs.y + raw[9 + i]);
+                        raw[i] = dec16(raw[i], kW36[i], Rs.x, one);
+                        raw[9 + i] = dec16(raw[9 + i], kW36[i], Rs.y, one);
                     }
                 } else {
 #pragma unroll
@@ -480,8 +528,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                         const float2 Rs = rrow[1 + kCy[i]][-kCx[i]];
                         const bool bb = (bbm >> i) & 1u;
                         const float Ro = bb ? Rown.x : Rs.x, Rw = bb ? Rown.y : Rs.y;
-                        raw[i] = kW36[i] * (Ro + raw[i]);
-                        raw[9 + i] = kW36[i] * (Rw + raw[9 + i]);
+                        raw[i] = dec16(raw[i], kW36[i], Ro, one);
+                        raw[9 + i] = dec16(raw[9 + i], kW36[i], Rw, one);
                     }
                 }
             }
@@ -511,8 +559,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                             S::unpack(S::load(base + o_extra), eo, ew);
                             if constexpr (S::kRef) {  // x + c_i, or the node itself
                                 const float2 Re = q < 0.5f ? rrow[1 - cy][cx] : rrow[1][0];
-                                eo = kW36[i] * (Re.x + eo);
-                                ew = kW36[i] * (Re.y + ew);
+                                eo = dec16(eo, kW36[i], Re.x, one);
+                                ew = dec16(ew, kW36[i], Re.y, one);
                             }
                         }
                         const float bo = ibb_blend(q, raw[i], eo);
@@ -550,8 +598,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                     const int cl = hbb_next ? ch : ch - hcx;
                     const float2 R = rref[sl * RW + cl];
                     const float w = dir_w36(hd);
-                    v0 = w * (R.x + v0);
-                    v1 = w * (R.y + v1);
+                    v0 = fmaf(v0, w, w * R.x);  // = w (R + v0): w is a power of two
+                    v1 = fmaf(v1, w, w * R.y);
                 }
                 if constexpr (EXT && !PY) {
                     if (P.wq && hbb_next) {
@@ -576,8 +624,8 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                                 const int cl = q < 0.5f ? ch + hcx : ch;
                                 const float2 Re = rref[sl * RW + cl];
                                 const float w = dir_w36(hd);
-                                eo = w * (Re.x + eo);
-                                ew = w * (Re.y + ew);
+                                eo = fmaf(eo, w, w * Re.x);
+                                ew = fmaf(ew, w, w * Re.y);
                             }
                         }
                         const float b0 = ibb_blend(q, v0, eo);
@@ -589,25 +637,30 @@ __device__ __forceinline__ void march(const void* __restrict__ fin, void* __rest
                     }
                 }
             }
-            float q0[9], q1[9];
-#pragma unroll
-            for (int j = 0; j < 9; ++j) {
-                q0[j] = __shfl(v0, (tid & ~15) + j, 64);
-                q1[j] = __shfl(v1, (tid & ~15) + j, 64);
-            }
+            float rh0, rh1;
             if constexpr (EXT && !PY) {
+                float q0[9], q1[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j) {
+                    q0[j] = __shfl(v0, (tid & ~15) + kHaloLane[j], 64);
+                    q1[j] = __shfl(v1, (tid & ~15) + kHaloLane[j], 64);
+                }
                 if (P.wq) {
                     float dm0 = 0.0f, dm1 = 0.0f;
 #pragma unroll
                     for (int j = 1; j < 9; ++j) {
-                        dm0 += __shfl(e0, (tid & ~15) + j, 64);
-                        dm1 += __shfl(e1, (tid & ~15) + j, 64);
+                        dm0 += __shfl(e0, (tid & ~15) + kHaloLane[j], 64);
+                        dm1 += __shfl(e1, (tid & ~15) + kHaloLane[j], 64);
                     }
                     q0[0] -= dm0;
                     q1[0] -= dm1;
                 }
+                rh0 = rho9(q0);
+                rh1 = rho9(q1);
+            } else {
+                rh0 = halo_rho(v0);
+                rh1 = halo_rho(v1);
             }
-            const float rh0 = rho9(q0), rh1 = rho9(q1);
             if (hgrp && hj == 0) {
                 const int col = hside ? wdt + 1 : 0;
                 ring[r & 3][0][col] = hfl ? rh0 : rs0;
