@@ -77,6 +77,40 @@ def test_channel_critical_pressure_vs_planar_young_laplace(gpu_available, lam):
     assert np.all(ratio >= 0.95) and np.all(ratio <= 2.0)
 
 
+def test_channel_critical_forcing_rises_with_the_potential_level(gpu_available):
+    """lambda = 128, the neutral wall with both potentials at a common level
+    of 0, 0.2575 (the map's), 0.5 and 1: the angle stays 90 deg (the two
+    components are symmetric) and the planar Young-Laplace value moves only
+    with the slug area, yet the critical forcing rises with the level
+    (measured 1.57, 1.73, 1.92, 2.28 of the analytic value), as the critical
+    Bo of the D3Q19 tube does (0.78 to 0.96): the wall's repulsion of both
+    components holds the slug on either lattice.  The ratio must rise
+    strictly with the level."""
+    from paper_1601_00918_amd import Simulation, binding
+    equil, budget = 20000, 300000
+    cfgs, g_yl = [], []
+    for level in (0.0, 0.2575, 0.5, 1.0):
+        cfg = dict(synth.config_channel(lam=128, theta=90.0), rho_s=(level, level))
+        sim = Simulation([cfg])
+        sim.step(equil)
+        rho = sim.moments(0)["rho"]
+        area = float((rho[0] / np.maximum(rho[0] + rho[1], 1e-30) > 0.9).sum())
+        dps, _ = yl.bond_critical_channel(128, cfg["h0"], cfg["a"], 90.0, area)
+        g_yl.append(dps * SIGMA / (RHO_BAR * cfg["nx"]))
+        cfgs.append(cfg)
+    probs = [binding.cp_problem(c, 0.5 * g, 3.0 * g, SIGMA, RHO_BAR, equil, budget)
+             for c, g in zip(cfgs, g_yl)]
+    res = binding.lbm_critical_pressure(
+        probs, binding.cp_options(rel_tol=0.01, chunk_steps=500, verify_bracket=1,
+                                  move_frac=1.5, creep_frac=1.25))
+    ratio = [r["g_crit"] / g for r, g in zip(res, g_yl)]
+    for c, r, q in zip(cfgs, res, ratio):
+        print("potential level %.4f g_LBM %.4e ratio %.3f flags %d"
+              % (c["rho_s"][0], r["g_crit"], q, r["flags"]), flush=True)
+    assert all(r["flags"] == 0 for r in res)
+    assert all(b > a for a, b in zip(ratio, ratio[1:]))
+
+
 def test_channel_critical_forcing_does_not_depend_on_the_viscosities(gpu_available):
     """Table 5 analogue in two dimensions: lambda = 128, the same slug with
     tau = (1, 1), (0.55, 1.5) and (1.5, 0.55) (oil-to-water viscosity ratios
