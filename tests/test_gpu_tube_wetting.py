@@ -296,6 +296,25 @@ def test_paper_tube_neutral_potential_level(gpu_available):
     assert abs(ratios[2] - 1.0) <= 0.1
 
 
+def test_paper_tube_potential_level_effect_falls_with_resolution(gpu_available):
+    """The neutral slug at one position at neck radii D = 6 and 12, both wall
+    potentials at the map's level (0.2575) and at 1: the depleted layer that a
+    strongly repelling wall builds is one or two nodes thick at any D, so what
+    level 1 adds to the ratio falls with the resolution (measured 0.126 at
+    D = 6, 0.107 at D = 8, 0.065 at D = 12, about 0.8 / D), while the ratio at the
+    map's level stays at 0.85-0.87.  The excess must shrink from D = 6 to 12."""
+    excess = {}
+    for D in (6, 12):
+        r = [_paper_tube_study(D, 90.0, 58.0, label="neutral, potentials %g" % level,
+                               positions=1, ramp=False, rho_s=(level, level))
+             for level in (0.2575, 1.0)]
+        assert all(f & ~1 == 0 for x in r for f in x["flags"])
+        q = [float(x["bo"][0] / x["bo0"][0]) for x in r]
+        excess[D] = q[1] - q[0]
+        print("D=%d ratio at the map level %.3f, at level 1 %.3f" % (D, q[0], q[1]), flush=True)
+    assert 0.0 < excess[12] < excess[6]
+
+
 def _sigma3(G):
     """Laplace-law surface tension of the D3Q19 model at interaction strength
     G: half the slope of the pressure jump against 1/R over oil droplets of
