@@ -12,6 +12,10 @@ the stored state is emulated.
     python tests/storage_floor.py            # prints the floors after 1000 steps
     python tests/storage_floor.py --write    # also stores them in
                                              # tests/golden/storage_floor.json
+    python tests/storage_floor.py --batch    # floors of the sampled instances
+                                             # of the 256-channel batch after 100
+                                             # steps, stored in
+                                             # tests/golden/storage_floor_batch.json
 
 Format "f32" rounds every population to binary32 instead: the floor of the
 FP32 storage itself (arithmetic still FP64).
@@ -114,7 +118,35 @@ def floor(cfg, fmt, steps=1000, seed=5):
             max(abs(M["mon"][k] / m0[k] - 1) for k in (0, 1)))
 
 
-if __name__ == "__main__":
+def batch_sample(cfgs):
+    """The sampled instances of the 256-channel batch: the first of each
+    wavelength."""
+    return [next(k for k, c in enumerate(cfgs) if c["lam"] == lam) for lam in (64, 128, 256, 512)]
+
+
+def write_batch_floors(steps=100):
+    import json
+    cfgs = synth.config_batch(n_inst=256, seed=1601)
+    table = {"steps": steps, "seed": 5, "fields": ["rho", "u", "p", "mass_drift"],
+             "batch": "synth.config_batch(n_inst=256, seed=1601)", "instances": {}}
+    for k in batch_sample(cfgs):
+        row = {"lam": int(cfgs[k]["lam"])}
+        for fmt in ("f16", "bf16"):
+            e = floor(cfgs[k], fmt, steps=steps)
+            row[fmt] = [float("%.3e" % v) for v in e]
+            print("instance %d (lambda %d) %-5s rho %.1e  u %.1e  p %.1e  mass drift %.1e"
+                  % ((k, cfgs[k]["lam"], fmt) + e), flush=True)
+        table["instances"][str(k)] = row
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "storage_floor_batch.json")
+    with open(out, "w") as fh:
+        json.dump(table, fh, indent=1)
+        fh.write("\n")
+
+
+if __name__ == "__main__" and "--batch" in sys.argv:
+    write_batch_floors()
+elif __name__ == "__main__":
     import json
     cfgs = {"droplet": synth.config_droplet(n=128, r=20.0),
             "poiseuille": synth.config_poiseuille(),

@@ -41,6 +41,45 @@ def test_full_batch_conserves_mass_and_matches_sampled_instances(gpu_available):
         assert eu <= velocity_bound(floor_u)
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_full_batch_in_16bit_storage_tracks_sampled_instances(gpu_available, storage):
+    """The 256-channel batch in the 16-bit formats, in the launch configuration
+    bench.py times with --storage: 100 steps without a bad node, each
+    species' mass within the 16-bit drift bounds, and the first instance of
+    each wavelength within four times its storage floor of the FP64 oracle
+    (floors from tests/storage_floor.py --batch, which emulates the format's
+    rounding on the oracle; the GPU's own random sequence and FP32 arithmetic
+    differ, hence the factor)."""
+    import json
+    import os
+    from paper_1601_00918_amd import Simulation
+    from tests.storage_floor import batch_sample
+    here = os.path.dirname(os.path.abspath(__file__))
+    table = json.load(open(os.path.join(here, "golden", "storage_floor_batch.json")))
+    steps = table["steps"]
+    cfgs = synth.config_batch(n_inst=256, seed=1601)
+    sim = Simulation(cfgs, storage=storage)
+    m0 = sim.monitors()
+    sim.step(steps)
+    m1 = sim.monitors()
+    drift = max(abs(b["mass"][s] / a["mass"][s] - 1) for a, b in zip(m0, m1) for s in range(2))
+    bad = sum(m["bad_nodes"] for m in m1)
+    print("%s, 256 instances, %d steps: max mass drift %.2e, bad nodes %d"
+          % (storage, steps, drift, bad), flush=True)
+    assert bad == 0 and drift <= (1e-5 if storage == "f16" else 5e-5)
+    for k in batch_sample(cfgs):
+        fr, fu, fp, _ = table["instances"][str(k)][storage]
+        L, mask, _ = oracle_lattice(cfgs[k])
+        L.step(steps)
+        ref, got = L.moments(), sim.moments(k)
+        erho = max(field_rel_err(ref["rho"], got["rho"], mask))
+        eu = max(field_rel_err(ref["u"], got["u"], mask))
+        ep = max(field_rel_err(ref["p"][None], got["p"][None], mask))
+        print("instance %d (lambda %d): rho %.2e (floor %.1e) u %.2e (floor %.1e) "
+              "p %.2e (floor %.1e)" % (k, cfgs[k]["lam"], erho, fr, eu, fu, ep, fp), flush=True)
+        assert erho <= 4 * fr and eu <= 4 * fu and ep <= 4 * fp
+
+
 @pytest.mark.parametrize("storage,G", [("f32", synth.G_DEFAULT), ("f16", 0.0)])
 def test_uniform_mixture_at_rest_stays_at_rest(gpu_available, storage, G):
     """No density gradient: the interaction force vanishes exactly and the rest
