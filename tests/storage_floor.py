@@ -12,6 +12,9 @@ the stored state is emulated.
     python tests/storage_floor.py            # prints the floors after 1000 steps
     python tests/storage_floor.py --write    # also stores them in
                                              # tests/golden/storage_floor.json
+    python tests/storage_floor.py --tube     # floors of the D3Q19 tube workload
+                                             # after 20 steps, stored in
+                                             # tests/golden/storage_floor_tube.json
     python tests/storage_floor.py --batch    # floors of the sampled instances
                                              # of the 256-channel batch after 100
                                              # steps, stored in
@@ -118,6 +121,104 @@ def floor(cfg, fmt, steps=1000, seed=5):
             max(abs(M["mon"][k] / m0[k] - 1) for k in (0, 1)))
 
 
+def oracle_lattice3(cfg):
+    """FP64 D3Q19 oracle lattice of a tube or box configuration."""
+    from oracle import lbm3d as o3
+    mask = synth.mask3_of(cfg)
+    p = o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                   rho_s=cfg["rho_s"], g=cfg["g"], periodic_yz=(cfg["kind"] == "box3d"))
+    return o3.Lattice3(p, mask, synth.rho03_of(cfg, mask)), mask
+
+
+def source_index3(mask, periodic_yz):
+    """D3Q19 counterpart of source_index, in the oracle's direction order;
+    also returns the weights w_i."""
+    from oracle import lbm3d as o3
+    cx, cy, cz, _, _ = o3.lattice()
+    nz, ny, nx = mask.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    own = (z * ny + y) * nx + x
+    idx = np.zeros((len(cx), nz, ny, nx), dtype=np.int64)
+    for i in range(len(cx)):
+        xs, ys, zs = (x - cx[i]) % nx, y - cy[i], z - cz[i]
+        if periodic_yz:
+            ys, zs = ys % ny, zs % nz
+        ok = (ys >= 0) & (ys < ny) & (zs >= 0) & (zs < nz)
+        ysc, zsc = np.clip(ys, 0, ny - 1), np.clip(zs, 0, nz - 1)
+        fluid = ok & (mask[zsc, ysc, xs] == 1)
+        idx[i] = np.where(fluid, (zsc * ny + ysc) * nx + xs, own)
+    c2 = np.asarray(cx) ** 2 + np.asarray(cy) ** 2 + np.asarray(cz) ** 2
+    w = np.where(c2 == 0, 1 / 3, np.where(c2 == 1, 1 / 18, 1 / 36))
+    return idx, w
+
+
+def reencode3(f, rho, mask, idx, w, fmt, rng):
+    """reencode on D3Q19: f [2, 19, nz, ny, nx] in the oracle's direction
+    order, w the weights (the rest direction has w = 1/3)."""
+    out = np.empty_like(f)
+    fluid = (mask == 1)
+    i0 = int(np.argmax(w))
+    W = w[:, None, None, None]
+    moving = [i for i in range(len(w)) if i != i0]
+    for s in range(2):
+        r32 = rho[s].astype(np.float32).astype(np.float64).ravel()
+        R = r32.astype(np.float16).astype(np.float64)
+        ref = R[idx]
+        d = _rne(f[s] / W - ref, fmt) * fluid[None]
+        dsum = np.zeros(r32.size)
+        np.add.at(dsum, idx[moving].ravel(), (W[moving] * d[moving]).ravel())
+        rest = (r32 - R - dsum) / w[i0]
+        d[i0] = (_sr(rest, fmt, rng) * fluid.ravel()).reshape(mask.shape)
+        out[s] = W * (ref + d)
+    out[:, :, ~fluid] = 0.0
+    return out
+
+
+def floor3(cfg, fmt, steps, seed=5):
+    """floor() for a D3Q19 configuration: max relative errors of rho, u, p."""
+    ref, mask = oracle_lattice3(cfg)
+    ref.step(steps)
+    R = ref.moments()
+    del ref
+    emu, _ = oracle_lattice3(cfg)
+    idx, w = source_index3(mask, cfg["kind"] == "box3d")
+    rng = np.random.default_rng(seed)
+    for _ in range(steps):
+        rho = emu.f.sum(axis=1)
+        emu.step(1)
+        emu.f[...] = reencode3(emu.f, rho, mask, idx, w, fmt, rng)
+    M = emu.moments()
+    m = mask.astype(bool)
+
+    def rel(a, b):
+        return max(float(np.abs(a[k][m] - b[k][m]).max() / np.abs(a[k][m]).max())
+                   for k in range(a.shape[0]))
+    return rel(R["rho"], M["rho"]), rel(R["u"], M["u"]), rel(R["p"][None], M["p"][None])
+
+
+def tube_config():
+    """The D3Q19 tube workload bench.py times."""
+    return synth.config_tube(lam=256, r0=40.0, a=16.0, nx=512, ny=128, nz=128, theta=60.0,
+                             tau=(1.0, 1.0), g=1e-6, slug_len=384, slug_x0=64)
+
+
+def write_tube_floors(steps=20):
+    import json
+    cfg = tube_config()
+    table = {"steps": steps, "seed": 5, "fields": ["rho", "u", "p"],
+             "workload": "D3Q19 tube 512 x 128 x 128, r(x) = 40 + 16 cos(2 pi x / 256), slug 384, "
+                         "theta 60 deg, g = 1e-6"}
+    for fmt in ("f16", "bf16"):
+        e = floor3(cfg, fmt, steps)
+        table[fmt] = [float("%.3e" % v) for v in e]
+        print("tube %-5s rho %.1e  u %.1e  p %.1e" % ((fmt,) + e), flush=True)
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "storage_floor_tube.json")
+    with open(out, "w") as fh:
+        json.dump(table, fh, indent=1)
+        fh.write("\n")
+
+
 def batch_sample(cfgs):
     """The sampled instances of the 256-channel batch: the first of each
     wavelength."""
@@ -146,6 +247,8 @@ def write_batch_floors(steps=100):
 
 if __name__ == "__main__" and "--batch" in sys.argv:
     write_batch_floors()
+elif __name__ == "__main__" and "--tube" in sys.argv:
+    write_tube_floors()
 elif __name__ == "__main__":
     import json
     cfgs = {"droplet": synth.config_droplet(n=128, r=20.0),

@@ -2,7 +2,8 @@
 launch configuration bench.py times (default tiling, one step launch per
 step): the lambda = 256 sinusoidal channel (1024 x 98, Sec. 3.4 in two
 dimensions) after 1000 steps, and the 512 x 128 x 128 D3Q19 sinusoidal tube
-(Sec. 3.4) after 50 steps, against the FP64 oracles."""
+(Sec. 3.4) after 50 steps, against the FP64 oracles; the tube also in the
+16-bit formats, against the oracle within its emulated storage floors."""
 import numpy as np
 import pytest
 
@@ -76,3 +77,40 @@ def test_tube_full_size_50_steps(gpu_available):
     assert err < 2e-7 * 50
     assert max(erho) <= 1e-5 and max(ep) <= 1e-5 and max(eu) <= 1e-5
     assert_monitors_match(ref["mon"], got["mon"], 1e-5, cfg["G"])
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_tube_full_size_16bit_storage(gpu_available, storage):
+    """The D3Q19 tube workload bench.py times with --storage f16 / bf16: rho,
+    u and p after 20 steps within four times the error the format's rounding
+    alone puts on the FP64 oracle (tests/storage_floor.py --tube emulates the
+    encoding on the oracle; the GPU's random sequence and FP32 arithmetic
+    differ, hence the factor), each species' mass within the 16-bit drift
+    bounds."""
+    import json
+    import os
+    from paper_1601_00918_amd.binding3d import Simulation3D
+    from tests.storage_floor import oracle_lattice3, tube_config
+    here = os.path.dirname(os.path.abspath(__file__))
+    table = json.load(open(os.path.join(here, "golden", "storage_floor_tube.json")))
+    steps = table["steps"]
+    fr, fu, fp = table[storage]
+    cfg = tube_config()
+    L, mask = oracle_lattice3(cfg)
+    sim = Simulation3D(cfg, storage=storage)
+    m0 = sim.monitors()["mass"]
+    sim.step(steps)
+    L.step(steps)
+    m1 = sim.monitors()["mass"]
+    ref, got = L.moments(), sim.moments()
+    m = mask.astype(bool)
+
+    def rel(a, b):
+        return max(float(np.abs(a[k][m] - b[k][m]).max() / np.abs(a[k][m]).max())
+                   for k in range(a.shape[0]))
+    erho, eu, ep = rel(ref["rho"], got["rho"]), rel(ref["u"], got["u"]), rel(ref["p"][None], got["p"][None])
+    drift = max(abs(m1[k] / m0[k] - 1) for k in range(2))
+    print("%s: rho %.2e (floor %.1e) u %.2e (floor %.1e) p %.2e (floor %.1e) mass drift %.1e"
+          % (storage, erho, fr, eu, fu, ep, fp, drift), flush=True)
+    assert erho <= 4 * fr and eu <= 4 * fu and ep <= 4 * fp
+    assert drift <= (1e-5 if storage == "f16" else 5e-5)
