@@ -254,6 +254,56 @@ def gpu_configs_mlups(steps=200, warmup=20):
     return out
 
 
+def other_workloads(steps=200, warmup=20):
+    """The other step launches the project measures, timed in the default run
+    like the headline one (HIP events on the launch stream): the 256-channel
+    batch in binary16 deviation storage, and the D3Q19 tube in FP32 and
+    binary16.  Each reports MLUPS, the fraction of 8 TB/s on its algorithmic
+    bytes per node, and the measured HBM traffic rate when a counter record
+    for the current kernel source exists."""
+    import torch
+    import synth
+    from paper_1601_00918_amd import Simulation
+    from paper_1601_00918_amd.binding3d import Simulation3D
+
+    def timed(sim, n):
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        sim.step(n)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def entry(name, storage, nf, ms, bpn, traffic):
+        return {"workload": name, "storage": storage, "fluid_nodes": nf,
+                "ms_per_step": round(ms, 5), "mlups": round(nf / ms / 1e3, 1),
+                "hbm_frac": round(bpn * nf / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": (round(traffic / (ms / 1e3) / 1e9, 1) if traffic else None)}
+
+    out = []
+    cfgs, desc = workload("batch")
+    nf = fluid_nodes(cfgs)
+    sim = Simulation(cfgs, storage="f16")
+    ms = timed(sim, steps)
+    del sim
+    out.append(entry("256-channel batch", "f16", nf, ms, BYTES_PER_NODE["f16"],
+                     measured_traffic("f16")))
+    cfg = tube_config()
+    nf3 = int(synth.mask3_of(cfg).sum())
+    for storage in ("f32", "f16"):
+        sim = Simulation3D(cfg, storage=storage)
+        ms = timed(sim, steps)
+        del sim
+        out.append(entry("D3Q19 tube 512x128x128", storage, nf3, ms,
+                         BYTES_PER_NODE_3D[storage],
+                         measured_traffic(storage, "step3_kernel_tube_traffic.txt",
+                                          KERNEL3_SOURCES)))
+    return out
+
+
 # Sources of the D2Q9 step kernel; the counter record names their hash.
 KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_store.h", "lbm_internal.h")
 KERNEL3_SOURCES = ("lbm3d_kernels.hip", "lbm_store.h", "lbm3d_internal.h")
@@ -535,7 +585,9 @@ def main():
     }
     if not args.no_cpu:
         if args.workload == "batch" and args.reg_order == 2 and args.storage == "f32":
+            del sim
             out["gpu_configs"] = gpu_configs_mlups()
+            out["other_workloads"] = other_workloads()
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
