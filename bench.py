@@ -375,9 +375,9 @@ def copy_calibration(steps, warmup, nbytes=2 << 30):
                  "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1)})
     assert torch.equal(src, dst)
     best = max(r["GBps"] for r in rows if r["kernel"] == "lbm_stream_copy")
-    print(json.dumps({"workload": "copy", "bytes_per_launch": 2 * nbytes, "runs": rows,
-                      "ceiling_GBps": best, "ceiling_frac_of_peak": round(best / HBM_PEAK_GBS, 4)}),
-          flush=True)
+    del src, dst
+    return {"workload": "copy", "bytes_per_launch": 2 * nbytes, "runs": rows,
+            "ceiling_GBps": best, "ceiling_frac_of_peak": round(best / HBM_PEAK_GBS, 4)}
 
 
 def solves_per_hour(args):
@@ -524,7 +524,7 @@ def main():
     from paper_1601_00918_amd import Simulation
 
     if args.workload == "copy":
-        copy_calibration(args.steps, args.warmup)
+        print(json.dumps(copy_calibration(args.steps, args.warmup)), flush=True)
         return
     if args.workload == "solves":
         print(json.dumps(solves_per_hour(args)), flush=True)
@@ -588,6 +588,13 @@ def main():
             del sim
             out["gpu_configs"] = gpu_configs_mlups()
             out["other_workloads"] = other_workloads()
+            # the practical ceiling of a 50:50 read/write stream on this device
+            cc = copy_calibration(20, 3)
+            out["copy_ceiling"] = {"GBps": cc["ceiling_GBps"],
+                                   "frac_of_peak": cc["ceiling_frac_of_peak"],
+                                   "step_traffic_frac_of_ceiling":
+                                       (round(out["roofline"]["traffic"] / cc["ceiling_GBps"], 4)
+                                        if out["roofline"]["traffic"] else None)}
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
