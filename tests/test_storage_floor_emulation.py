@@ -1,6 +1,6 @@
 """The storage-rounding emulation that the 16-bit floors come from
-(tests/storage_floor.py), checked on its own: source indices by brute force on
-a tiny tube, every re-encoded population within half a unit in the last place
+(tests/storage_floor.py), checked on its own, on D3Q19 and D2Q9: source
+indices by brute force on a tiny tube and channel, every re-encoded population within half a unit in the last place
 of its deviation, and each node's stored mass equal to its density up to the
 rounding of the stochastic rest remainder.  CPU only."""
 import numpy as np
@@ -73,3 +73,53 @@ def test_reencode3_rounds_each_deviation_and_keeps_node_mass(fmt, ulp):
         rest_dev = np.abs(out[s][i0].ravel() / w[i0] - R)
         assert np.all(np.abs(emitted - r32)[fluid.ravel()] <=
                       (w[i0] * (ulp * rest_dev + 2.0 ** -24) + 1e-15)[fluid.ravel()])
+
+
+def _tiny_channel():
+    cfg = synth.config_channel(lam=16, theta=90.0)
+    return cfg, synth.mask_of(cfg)
+
+
+def test_source_index_by_brute_force():
+    cfg, mask = _tiny_channel()
+    idx = sf.source_index(mask, False)
+    ny, nx = mask.shape
+    for i in range(9):
+        for y in range(ny):
+            for x in range(nx):
+                xs, ys = (x - sf.CX[i]) % nx, y - sf.CY[i]
+                inside = 0 <= ys < ny and mask[ys, xs] == 1
+                assert idx[i, y, x] == (ys * nx + xs if inside else y * nx + x)
+
+
+@pytest.mark.parametrize("fmt,ulp", [("f16", 2.0 ** -10), ("bf16", 2.0 ** -7), ("f32", 2.0 ** -23)])
+def test_reencode_rounds_each_deviation_and_keeps_node_mass(fmt, ulp):
+    cfg, mask = _tiny_channel()
+    idx = sf.source_index(mask, False)
+    rng = np.random.default_rng(4)
+    fluid = mask == 1
+    rho = np.stack([1.0 + 0.05 * rng.random(mask.shape), 0.03 * (1 + 0.5 * rng.random(mask.shape))])
+    rho *= fluid
+    W = sf.W[:, None, None]
+    f = np.zeros((2, 9) + mask.shape)
+    for s in range(2):
+        f[s] = W * rho[s].ravel()[idx] * (1 + 0.03 * rng.standard_normal(idx.shape))
+    f *= fluid
+    out = sf.reencode(f, rho, mask, idx, fmt, np.random.default_rng(9))
+    if fmt == "f32":   # every population rounded to binary32
+        assert np.all(np.abs(out - f) <= 0.5 * ulp * np.abs(f))
+        return
+    sub = 2.0 ** -25 if fmt == "f16" else 0.0
+    for s in range(2):
+        R = rho[s].astype(np.float32).astype(np.float16).astype(np.float64).ravel()
+        dev = f[s] / W - R[idx]
+        err = np.abs(out[s] - f[s]) / W
+        bound = (0.5 * ulp + 2.0 ** -23) * np.abs(dev) + sub + 1e-15
+        assert np.all(err[1:][:, fluid] <= bound[1:][:, fluid])
+        emitted = np.zeros(mask.size)
+        np.add.at(emitted, idx[1:].ravel(), out[s][1:].ravel())
+        emitted += out[s][0].ravel()
+        r32 = rho[s].astype(np.float32).astype(np.float64).ravel()
+        rest_dev = np.abs(out[s][0].ravel() / sf.W[0] - R)
+        assert np.all(np.abs(emitted - r32)[fluid.ravel()] <=
+                      (sf.W[0] * (ulp * rest_dev + 2.0 ** -24) + 1e-15)[fluid.ravel()])
