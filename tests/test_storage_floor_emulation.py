@@ -1,8 +1,9 @@
 """The storage-rounding emulation that the 16-bit floors come from
 (tests/storage_floor.py), checked on its own, on D3Q19 and D2Q9: source
-indices by brute force on a tiny tube and channel, every re-encoded population within half a unit in the last place
-of its deviation, and each node's stored mass equal to its density up to the
-rounding of the stochastic rest remainder.  CPU only."""
+indices by brute force on a tiny tube and channel, every re-encoded
+population within half a unit in the last place of its deviation, and each
+node's stored mass equal to its density up to the rounding of the stochastic
+rest remainder.  CPU only."""
 import numpy as np
 import pytest
 
