@@ -2,8 +2,9 @@
 launch configuration bench.py times (default tiling, one step launch per
 step): the lambda = 256 sinusoidal channel (1024 x 98, Sec. 3.4 in two
 dimensions) after 1000 steps, and the 512 x 128 x 128 D3Q19 sinusoidal tube
-(Sec. 3.4) after 50 steps, against the FP64 oracles; the tube also in the
-16-bit formats, against the oracle within its emulated storage floors."""
+(Sec. 3.4) after 50 steps, against the FP64 oracles; the tube also with
+interpolated walls, and in the 16-bit formats against the oracle within its
+emulated storage floors."""
 import numpy as np
 import pytest
 
@@ -77,6 +78,45 @@ def test_tube_full_size_50_steps(gpu_available):
     assert err < 2e-7 * 50
     assert max(erho) <= 1e-5 and max(ep) <= 1e-5 and max(eu) <= 1e-5
     assert_monitors_match(ref["mon"], got["mon"], 1e-5, cfg["G"])
+
+
+def test_tube_full_size_interpolated_walls_10_steps(gpu_available):
+    """The same tube with its wall at the analytic position (interpolated
+    bounce-back, lbm3d_geom.wall_interp): the wall table and the wall kernels
+    at full size.  Every population after 10 steps within 2e-7 per step of
+    the oracle's interpolated bounce-back, rho, u and p to 1e-5 (10 steps: the
+    oracle recomputes every link fraction each step, several seconds per
+    step at this size)."""
+    from paper_1601_00918_amd.binding3d import C3, Simulation3D
+    steps = 10
+    cfg = synth.config_tube(lam=256, r0=40.0, a=16.0, nx=512, ny=128, nz=128, theta=60.0,
+                            tau=(1.0, 1.0), g=1e-6, slug_len=384, slug_x0=64, wall_interp=True)
+    mask = synth.mask3_of(cfg)
+    wall = (0.5 * (cfg["ny"] - 1), 0.5 * (cfg["nz"] - 1), cfg["r0"], cfg["a"], cfg["lam"])
+    p = o3.Params3(cfg["nx"], cfg["ny"], cfg["nz"], tau=cfg["tau"], G=cfg["G"],
+                   rho_s=cfg["rho_s"], g=cfg["g"], wall=wall)
+    L = o3.Lattice3(p, mask, synth.rho03_of(cfg, mask))
+    sim = Simulation3D(cfg)
+    print("interpolated-wall tube tiling", sim.tiling(), flush=True)
+    sim.step(steps)
+    L.step(steps)
+    cx, cy, cz, _, _ = o3.lattice()
+    oc = np.stack([cx, cy, cz], axis=1)
+    perm = [int(np.nonzero((oc == c).all(axis=1))[0][0]) for c in C3]
+    f = np.empty_like(L.f)
+    f[:, perm] = sim.populations()
+    err = float(np.abs(f - L.f).max())
+    del f
+    ref, got = L.moments(), sim.moments()
+    m = mask.astype(bool)
+
+    def rel(a, b):
+        return [float(np.abs(a[k][m] - b[k][m]).max() / np.abs(a[k][m]).max())
+                for k in range(a.shape[0])]
+    erho, eu, ep = rel(ref["rho"], got["rho"]), rel(ref["u"], got["u"]), rel(ref["p"][None], got["p"][None])
+    print("max|df| %.3e rho %s u %s p %s" % (err, erho, eu, ep), flush=True)
+    assert err < 2e-7 * steps
+    assert max(erho) <= 1e-5 and max(ep) <= 1e-5 and max(eu) <= 1e-5
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
