@@ -44,6 +44,42 @@ def test_channel_lambda256_1000_steps(gpu_available, theta):
     assert_monitors_match(ref["mon"], got["mon"], velocity_bound(floor["u"]), cfg["G"])
 
 
+def test_channel_lambda256_interpolated_walls_1000_steps(gpu_available):
+    """The lambda = 256 channel at theta = 120 deg with its walls at the
+    analytic position (interpolated bounce-back, lbm_geom.wall_interp), after
+    1000 steps: rho and p to four times their binary32 storage floor (the
+    sharp-start floor of the half-way case above), u to the same bound or
+    1e-4, whichever is larger (the wall blends' FP32 arithmetic perturbs the
+    contact lines' spurious currents, as on the lambda = 64 channel)."""
+    from oracle import lbm as orc
+    from paper_1601_00918_amd import Simulation
+    cfg = dict(synth.config_channel(lam=256, theta=120.0, g=2e-6, tau=(0.8, 1.2)),
+               wall_interp=1)
+    mask = synth.mask_of(cfg)
+
+    def oracle():
+        wall = (0.5 * (cfg["ny"] - 1), cfg["h0"], cfg["a"], cfg["lam"])
+        p = orc.Params(cfg["nx"], cfg["ny"], tau=cfg["tau"], G=cfg["G"], rho_s=cfg["rho_s"],
+                       g=cfg["g"], wall=wall)
+        return orc.Lattice(p, mask, synth.rho0_of(cfg, mask))
+    L = oracle()
+    sim = Simulation([cfg])
+    sim.step(1000)
+    L.step(1000)
+    ref, got = L.moments(), sim.moments(0)
+    erho = field_rel_err(ref["rho"], got["rho"], mask)
+    eu = field_rel_err(ref["u"], got["u"], mask)
+    ep = field_rel_err(ref["p"][None], got["p"][None], mask)
+    floor = fp32_storage_floor(oracle, 1000, mask)
+    print("interpolated walls: rho %s u %s p %s; storage floors %s" % (erho, eu, ep, floor),
+          flush=True)
+    assert max(erho) <= velocity_bound(floor["rho"])
+    assert max(ep) <= velocity_bound(floor["p"])
+    u_bound = max(velocity_bound(floor["u"]), 1e-4)
+    assert max(eu) <= u_bound
+    assert_monitors_match(ref["mon"], got["mon"], u_bound, cfg["G"])
+
+
 def test_tube_full_size_50_steps(gpu_available):
     """The D3Q19 tube workload bench.py times (512 x 128 x 128, r(x) = 40 +
     16 cos(2 pi x / 256), slug of 384 nodes, theta 60 deg, g = 1e-6): every
