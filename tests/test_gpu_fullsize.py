@@ -41,6 +41,38 @@ def test_full_batch_conserves_mass_and_matches_sampled_instances(gpu_available):
         assert eu <= velocity_bound(floor_u)
 
 
+def test_full_batch_third_order_matches_sampled_instances(gpu_available):
+    """The 256-channel batch with the third-order regularization (what
+    bench.py --reg-order 3 times): mass kept and the first instance of each
+    wavelength element by element against the oracle's third-order step after
+    100 steps (rho, p to 1e-5, u to the velocity bound of its binary32 storage
+    floor)."""
+    from paper_1601_00918_amd import Simulation
+    cfgs = [dict(c, reg_order=3) for c in synth.config_batch(n_inst=256, seed=1601)]
+    sim = Simulation(cfgs)
+    m0 = sim.monitors()
+    sim.step(100)
+    m1 = sim.monitors()
+    drift = max(abs(b["mass"][s] / a["mass"][s] - 1) for a, b in zip(m0, m1) for s in range(2))
+    bad = sum(m["bad_nodes"] for m in m1)
+    print("third order, 256 instances, 100 steps: max mass drift %.2e, bad nodes %d"
+          % (drift, bad), flush=True)
+    assert bad == 0 and drift <= 1e-6
+    sampled = [next(k for k, c in enumerate(cfgs) if c["lam"] == lam) for lam in (64, 128, 256, 512)]
+    for k in sampled:
+        L, mask, _ = oracle_lattice(cfgs[k])
+        L.step(100)
+        ref, got = L.moments(), sim.moments(k)
+        erho = max(field_rel_err(ref["rho"], got["rho"], mask))
+        ep = max(field_rel_err(ref["p"][None], got["p"][None], mask))
+        eu = max(field_rel_err(ref["u"], got["u"], mask))
+        floor_u = fp32_storage_floor_u(lambda: oracle_lattice(cfgs[k])[0], 100, mask)
+        print("instance %d (lambda %d): rho %.2e u %.2e (floor %.2e) p %.2e" % (
+            k, cfgs[k]["lam"], erho, eu, floor_u, ep), flush=True)
+        assert erho <= 1e-5 and ep <= 1e-5
+        assert eu <= velocity_bound(floor_u)
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_full_batch_in_16bit_storage_tracks_sampled_instances(gpu_available, storage):
     """The 256-channel batch in the 16-bit formats, in the launch configuration
