@@ -15,10 +15,12 @@ pytestmark = pytest.mark.gpu
 def _cases():
     return {"island64": synth.config_bypass(lam=64, theta=120.0, g=1e-5, tau=(0.8, 1.2)),
             "island128": synth.config_bypass(lam=128, theta=60.0, g=4e-6, island_h=5,
-                                             island_len=40)}
+                                             island_len=40),
+            # the C3 size (lambda = 256, 1024 x 98)
+            "island256": synth.config_bypass(lam=256, theta=120.0, g=2e-6, tau=(0.8, 1.2))}
 
 
-@pytest.mark.parametrize("which", ["island64", "island128"])
+@pytest.mark.parametrize("which", ["island64", "island128", "island256"])
 def test_fluid_mask_and_mask_geometry(gpu_available, which):
     """The library's voxelisation of the island equals the synthetic mask
     (two runs in the island columns), and the same mask passed as a mask
@@ -38,7 +40,7 @@ def test_fluid_mask_and_mask_geometry(gpu_available, which):
     assert np.array_equal(a.populations(0), b.populations(0))
 
 
-@pytest.mark.parametrize("which", ["island64", "island128"])
+@pytest.mark.parametrize("which", ["island64", "island128", "island256"])
 def test_few_steps_and_1000_steps_match_oracle(gpu_available, which):
     from paper_1601_00918_amd import Simulation
     cfg = _cases()[which]
