@@ -97,6 +97,8 @@ def bench_tube(args):
     from paper_1601_00918_amd.binding3d import Simulation3D
 
     cfg = tube_config()
+    if args.wall_interp:
+        cfg = dict(cfg, wall_interp=True)
     nf = int(synth.mask3_of(cfg).sum())
     sim = Simulation3D(cfg, storage=args.storage)
     if args.tiling:
@@ -123,7 +125,7 @@ def bench_tube(args):
           (ms_per_step, wall, mlups, mon["bad_nodes"]), file=sys.stderr, flush=True)
     bytes_per_launch = BYTES_PER_NODE_3D[args.storage] * nf
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
-    traffic = (None if args.tiling else
+    traffic = (None if args.tiling or args.wall_interp else
                measured_traffic(args.storage, "step3_kernel_tube_traffic.txt", KERNEL3_SOURCES))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -131,7 +133,8 @@ def bench_tube(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": "D3Q19 sinusoidal tube 512x128x128, r(x) = 40 + 16 cos(2 pi x/256), "
-                               "oil slug 384, theta 60 deg, g = 1e-6",
+                               "oil slug 384, theta 60 deg, g = 1e-6" +
+                               (", interpolated walls" if args.wall_interp else ""),
                    "fluid_nodes": nf, "storage": args.storage, "tiling": list(sim.tiling()[:3])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -499,6 +502,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--storage", default="f32")
+    ap.add_argument("--wall-interp", action="store_true",
+                    help="--workload tube3d: the tube's wall at its analytic position "
+                         "(interpolated bounce-back)")
     ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tiling", default=None,
