@@ -134,7 +134,7 @@ lbm_status lbm3d_fluid_mask(lbm3d_ctx* ctx, uint8_t* mask);
 
 /* Tiling of the step kernel: one workgroup advances a tile of bx x by nodes
  * (x, y) through a strip of strip_planes planes along z.  (bx, by) is one of
- * (16, 12) (default; (32, 8) with interpolated walls and 16-bit storage),
+ * (16, 12) (default),
  * (32, 16), (64, 8), (32, 8); strip_planes >= 4 (default 8).
  * Results do not depend on the tiling (bit for bit).  Synchronises. */
 lbm_status lbm3d_set_tiling(lbm3d_ctx* ctx, int32_t bx, int32_t by, int32_t strip_planes);

@@ -615,10 +615,10 @@ __device__ __forceinline__ void march3(const void* __restrict__ fin, void* __res
 }
 
 // Workgroups of at most 256 threads run three per CU (three waves per SIMD:
-// at most 168 registers) except with interpolated walls, which need more.
+// at most 168 registers), two with interpolated walls (at most 256).
 template <int BXI, int BYI, int MODE, typename T, bool WALL>
 __global__ void __launch_bounds__((Tile<BXI, BYI>::NT),
-                                  (Tile<BXI, BYI>::NT <= 256 && !WALL ? 3 : 1))
+                                  (Tile<BXI, BYI>::NT <= 256 ? (WALL ? 2 : 3) : 1))
 step3_kernel(const void* __restrict__ fin, void* __restrict__ fout, const Inst3Dev P,
              const Item3* __restrict__ items, const uint32_t* __restrict__ runs,
              double* __restrict__ partial, double* __restrict__ stage, uint32_t seed)

@@ -533,11 +533,11 @@ lbm_status lbm3d_init(const lbm3d_geom* geom, const lbm3d_fluid* fluid,
     c->L = L;
     c->stream = (hipStream_t)hip_stream;
     c->runs = std::move(runs);
-    // Default tiles, measured on the 512 x 128 x 128 tube: 16 x 12 (four-wave
-    // workgroups, two or three per CU); the interpolated-wall step holds more
-    // live values per node and spills in the 612-thread tiles, and with 16-bit
-    // storage it runs best at 32 x 8.
-    c->tile = (geom->wall_interp && fmt != LBM_STORE_F32) ? 2 : 3;
+    // Default tile, measured on the 512 x 128 x 128 tube in every storage
+    // format, with and without interpolated walls: 16 x 12 (four-wave
+    // workgroups, three per CU, two with interpolated walls, which hold more
+    // live values per node and spill in the 612-thread tiles).
+    c->tile = 3;
     c->P = make_inst(*geom, fmt);
     fill_fluid(c->P, *fluid);
     char* ws = (char*)device_workspace;
