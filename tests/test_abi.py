@@ -146,6 +146,12 @@ def test_bench_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     if t is not None:           # the record matches the current kernel source
         assert t == expect
     assert bench.measured_traffic("bf16") is None   # never profiled
+    # the D3Q19 tube record, keyed by the D3Q19 kernel sources
+    rec3 = json.load(open(os.path.join(ROOT, "profiles", "step3_kernel_tube_traffic.txt")))
+    t3 = bench.measured_traffic("f16", "step3_kernel_tube_traffic.txt", bench.KERNEL3_SOURCES)
+    if t3 is not None:
+        assert t3 == 1024.0 * (rec3["f16"]["fetch_kib"] * rec3["fetch_scale"] +
+                               rec3["f16"]["write_kib"] * rec3["write_scale"])
     # a changed kernel source voids the record
     fake_root = tmp_path
     (fake_root / "profiles").mkdir()
